@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the examples.
+
+This module only draws inputs: baseline coordinates of a synthetic array,
+channel frequencies, images and visibilities.  It contains none of the
+gridding method's arithmetic, so that the product and the oracle can both be
+fed from it without sharing code.
+
+Array model (a stand-in for a real measurement set; the paper's MeerKAT data
+are not available): antennas on a plane at latitude -30 deg observing a phase
+centre at declination -60 deg, hour angles symmetric about transit, textbook
+east-north-up -> equatorial baseline rotation.  Rows are time-major (all
+baselines of one dump, then the next dump), as in a measurement set.
+"""
+import math
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+ARCMIN = math.pi / (180.0 * 60.0)
+DEG = math.pi / 180.0
+
+
+def antennas_disk(rng, n_ant, diameter_m):
+    """East/north positions uniform in a disk."""
+    r = 0.5 * diameter_m * np.sqrt(rng.random(n_ant))
+    th = 2.0 * np.pi * rng.random(n_ant)
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def antennas_logradial(rng, n_ant, r_min_m, ratio):
+    """East/north positions with log-uniform radius r_min * ratio**U."""
+    r = r_min_m * ratio ** rng.random(n_ant)
+    th = 2.0 * np.pi * rng.random(n_ant)
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def earth_rotation_uvw(ant_en, hours, n_dumps, lat_deg=-30.0, dec_deg=-60.0):
+    """uvw [n_dumps * n_baselines, 3] in metres for hour angles spread evenly
+    over ``hours`` centred on transit."""
+    n_ant = ant_en.shape[0]
+    i, j = np.triu_indices(n_ant, k=1)
+    de = ant_en[j, 0] - ant_en[i, 0]
+    dn = ant_en[j, 1] - ant_en[i, 1]
+    lat, dec = lat_deg * DEG, dec_deg * DEG
+    lx = -math.sin(lat) * dn
+    ly = de
+    lz = math.cos(lat) * dn
+    half = 0.5 * hours * 15.0 * DEG
+    if n_dumps == 1:
+        ha = np.zeros(1)
+    else:
+        ha = np.linspace(-half, half, n_dumps)
+    sh, ch = np.sin(ha)[:, None], np.cos(ha)[:, None]
+    u = sh * lx[None, :] + ch * ly[None, :]
+    v = -math.sin(dec) * ch * lx[None, :] + math.sin(dec) * sh * ly[None, :] + math.cos(dec) * lz[None, :]
+    w = math.cos(dec) * ch * lx[None, :] - math.cos(dec) * sh * ly[None, :] + math.sin(dec) * lz[None, :]
+    return np.stack([u.ravel(), v.ravel(), w.ravel()], axis=1)
+
+
+def channels(f_lo, f_hi, n_chan):
+    if n_chan == 1:
+        return np.array([0.5 * (f_lo + f_hi)])
+    return np.linspace(f_lo, f_hi, n_chan)
+
+
+def complex_gaussian(rng, shape, dtype=np.complex128):
+    real_dt = np.float32 if dtype == np.complex64 else np.float64
+    out = np.empty(shape, dtype=dtype)
+    out.real = rng.standard_normal(shape, dtype=real_dt)
+    out.imag = rng.standard_normal(shape, dtype=real_dt)
+    return out
+
+
+def point_sources(rng, npix_x, npix_y, n_src, dtype=np.float64):
+    """Image with n_src sources at distinct random pixel centres, fluxes
+    exp(N(0, 1)) (log-normal)."""
+    img = np.zeros((npix_x, npix_y), dtype=dtype)
+    flat = rng.choice(npix_x * npix_y, size=n_src, replace=False)
+    img.ravel()[flat] = np.exp(rng.standard_normal(n_src))
+    return img
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def small_plain(seed=1):
+    """64x64 image, 0.5 arcmin pixels, one channel at 1 GHz, 2000 visibilities
+    with u, v ~ U[-2, 2] km and w ~ U[-0.3, 0.3] km; complex Gaussian
+    visibilities, N(0, 1) image."""
+    rng = np.random.default_rng(seed)
+    nrow = 2000
+    uvw = np.empty((nrow, 3))
+    uvw[:, 0:2] = rng.uniform(-2000.0, 2000.0, (nrow, 2))
+    uvw[:, 2] = rng.uniform(-300.0, 300.0, nrow)
+    freq = np.array([1e9])
+    npix = 64
+    pix = 0.5 * ARCMIN
+    vis = complex_gaussian(rng, (nrow, 1))
+    img = rng.standard_normal((npix, npix))
+    return dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+                vis=vis, dirty=img, name="plain-64x64-2000vis")
+
+
+def accuracy_setup(seed=0, npix=512, fov_deg=15.0, nvis=1000, freq_hz=1e9):
+    """Validation set-up of Sect. 5: npix^2 image over fov_deg^2, one channel,
+    uvw uniform in [-a, a] with a = lambda / (2 pixsize) metres (reading of the
+    garbled definition of a), data and image uniform in [-0.5, 0.5]."""
+    rng = np.random.default_rng(seed)
+    pix = fov_deg * DEG / npix
+    lam = C_LIGHT / freq_hz
+    a = lam / (2.0 * pix)
+    uvw = rng.uniform(-a, a, (nvis, 3))
+    vis = (rng.uniform(-0.5, 0.5, (nvis, 1)) + 1j * rng.uniform(-0.5, 0.5, (nvis, 1)))
+    img = rng.uniform(-0.5, 0.5, (npix, npix))
+    return dict(uvw=uvw, freq=np.array([freq_hz]), npix_x=npix, npix_y=npix, pixsize_x=pix,
+                pixsize_y=pix, vis=vis, dirty=img, name=f"accuracy-{npix}-{fov_deg}deg-{nvis}vis")
+
+
+def wide_field(seed=2, n_dumps=2880, n_chan=16, npix=2048, fov_deg=10.0, n_src=500,
+               with_vis=True, vis_dtype=np.complex64):
+    """Wide-field workload: 64 antennas uniform in a 5 km disk, 8 h at 10 s dumps
+    (2880 x 2016 = 5,806,080 rows), 16 channels over 0.9-1.7 GHz
+    (92,897,280 visibilities), 2048^2 image over 10 deg with 500 log-normal
+    point sources."""
+    rng = np.random.default_rng(seed)
+    ant = antennas_disk(rng, 64, 5000.0)
+    uvw = earth_rotation_uvw(ant, 8.0, n_dumps)
+    freq = channels(0.9e9, 1.7e9, n_chan)
+    pix = fov_deg * DEG / npix
+    img = point_sources(rng, npix, npix, n_src)
+    out = dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+               dirty=img, name=f"wide-field-{npix}^2-{uvw.shape[0] * n_chan}vis")
+    if with_vis:
+        out["vis"] = complex_gaussian(rng, (uvw.shape[0], n_chan), vis_dtype)
+    return out
+
+
+def large(seed=3, n_dumps=1000, n_chan=8, npix=8192, fov_deg=30.0, with_data=True):
+    """Large workload: 256 antennas with log-radial radii 20 m * 500^U (up to
+    10 km), 4 h in 1000 dumps (32,640,000 rows), 8 channels over 0.9-1.7 GHz
+    (261,120,000 visibilities), 8192^2 image over 30 deg; Gaussian image and
+    complex64 Gaussian visibilities."""
+    rng = np.random.default_rng(seed)
+    ant = antennas_logradial(rng, 256, 20.0, 500.0)
+    uvw = earth_rotation_uvw(ant, 4.0, n_dumps)
+    freq = channels(0.9e9, 1.7e9, n_chan)
+    pix = fov_deg * DEG / npix
+    out = dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+               name=f"large-{npix}^2-{uvw.shape[0] * n_chan}vis")
+    if with_data:
+        out["dirty"] = rng.standard_normal((npix, npix), dtype=np.float32)
+        out["vis"] = complex_gaussian(rng, (uvw.shape[0], n_chan), np.complex64)
+    return out
+
+
+def differentiation(seed=5, n_dumps=620, n_chan=4, npix=1024, n_src=100, noise_frac=0.1):
+    """Differentiation workload: 64 antennas (5 km disk), 2 h in 620 dumps x
+    2016 baselines x 4 channels (4,999,680 visibilities), 1024^2 image with
+    pixel size 10 deg / 2048 (5 deg field), a 100-source log-normal sky."""
+    rng = np.random.default_rng(seed)
+    ant = antennas_disk(rng, 64, 5000.0)
+    uvw = earth_rotation_uvw(ant, 2.0, n_dumps)
+    freq = channels(0.9e9, 1.7e9, n_chan)
+    pix = 10.0 * DEG / 2048
+    sky = point_sources(rng, npix, npix, n_src)
+    return dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+                sky=sky, noise_frac=noise_frac, rng=rng, name=f"diff-{npix}^2")
