@@ -1,0 +1,191 @@
+/*
+ * wgrid -- w-gridding radio-interferometry measurement operator for AMD
+ * MI355X (gfx950), after Arras, Reinecke, Westermann & Ensslin,
+ * "Efficient wide-field radio interferometry response" (arXiv:2010.10122).
+ *
+ * C ABI.  All array arguments are plain pointers: "device" means HIP device
+ * memory of the current device, "host" means ordinary host memory.  Every
+ * array is C-contiguous, row-major.  No call throws; every int-returning
+ * call returns WG_OK (0) or a negative WG_E* code, and wg_strerror() turns a
+ * code into text (for WG_EHIP it includes the last HIP error seen).
+ *
+ * Operators (Sect. 2, eq. 3; Sect. 3.1):
+ *   degridding  R   : real image [npix_x][npix_y] -> visibilities [n_rows][n_chan]
+ *                     d_k = sum_lm I_lm / n_lm exp(-2 pi i [u_k l + v_k m - w_k (n_lm - 1)])
+ *   gridding    R^H : visibilities -> real image, the adjoint with the real part
+ *                     taken (Sect. 5, direct adjoint; Sect. 5.1, adjointness)
+ * computed approximately to a requested accuracy epsilon by w-gridding:
+ * convolution with the modified ES kernel (eq. semicircle2) on an
+ * oversampled uv grid and on a stack of w-planes, 2-D FFTs per plane,
+ * w-screens and the correction 1/(n Psi) (eqs. R1-R3, Rad1-Rad2).
+ *
+ * Coordinates: pixel (p, q) has l = (p - npix_x/2) * pixsize_x and
+ * m = (q - npix_y/2) * pixsize_y (Sect. 2, sets L and M); the x axis pairs
+ * with u.  Effective coordinates are uvw[r] * freq[c] / 299792458 (Sect. 2).
+ */
+#ifndef WGRID_H
+#define WGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define WG_OK            0
+#define WG_EINVAL       -1   /* invalid argument (see each call)                      */
+#define WG_ENOMEM       -2   /* an allocation failed                                  */
+#define WG_EHIP         -3   /* a HIP runtime call or kernel launch failed            */
+#define WG_EUNSUPPORTED -4   /* valid request outside what this build implements     */
+
+/* ---- precision --------------------------------------------------------- */
+#define WG_F32 0   /* complex64 visibilities, float32 image (epsilon >= 1e-5)      */
+#define WG_F64 1   /* complex128 visibilities, float64 image (epsilon > 2e-13)     */
+
+/* Optional caller allocator for device memory (e.g. a framework's caching
+ * allocator).  alloc returns NULL on failure.  Both NULL -> hipMalloc/hipFree. */
+typedef void *(*wg_alloc_fn)(void *ctx, size_t bytes);
+typedef void (*wg_free_fn)(void *ctx, void *ptr);
+
+typedef struct wg_plan wg_plan;   /* opaque, immutable after creation */
+
+/* Plan description: the problem statement of the paper's interface
+ * (Appendix B: uvw, freq, mask, npix, pixsize, epsilon, do_wstacking) plus
+ * the precision the operator runs in. */
+typedef struct {
+    const double  *uvw;          /* device [n_rows][3], baseline coordinates in metres
+                                    (may be NULL when n_rows == 0)                     */
+    const double  *freq;         /* device [n_chan], channel frequencies in Hz (> 0)    */
+    const uint8_t *mask;         /* device [n_rows][n_chan] or NULL; !=0 selects        */
+    int64_t        n_rows;       /* >= 0                                                */
+    int64_t        n_chan;       /* >= 1; n_rows * n_chan < 2^32                        */
+    int            npix_x;       /* image size, even and >= 32 (Appendix B)             */
+    int            npix_y;
+    double         pixsize_x;    /* pixel size in radians, > 0                          */
+    double         pixsize_y;
+    double         epsilon;      /* requested accuracy (relative L2)                    */
+    int            precision;    /* WG_F32 or WG_F64                                    */
+    int            do_wgridding; /* 0: w treated as zero (narrow field), else w-gridding */
+    int            alpha;        /* 0 = automatic; else force kernel support (4,7,8,12,16) */
+    double         sigma;        /* 0 = automatic; else force oversampling (table row)  */
+    int            planes_per_batch; /* 0 = automatic; w-planes processed per batch     */
+    void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
+    wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
+    wg_free_fn     free;
+    void          *alloc_ctx;
+} wg_plan_desc;
+
+/* Create a plan.  Chooses the kernel (alpha, sigma, beta, mu) from the
+ * Appendix-A tables with the cost model of Sect. 4.1 unless forced, derives
+ * the grid size N = good_size(ceil(sigma n)) (Sect. 2), the w-plane spacing
+ * dw = 1/(2 sigma max|n-1|), the first plane w_o and the plane count N_w
+ * (Sect. 2, eq. wcirc), builds the piecewise-polynomial kernel (Sect. 4.2),
+ * the correction factors and the visibility index (Sect. 4.3) on the device.
+ * Synchronises the stream once (to read the w range and the active count).
+ * The uvw/freq/mask arrays are read during creation and again by every
+ * apply call: they must stay alive and unchanged while the plan is used.
+ * Errors: WG_EINVAL for NULL desc/out/uvw/freq, odd or < 32 npix, pixsize
+ *   <= 0, epsilon outside (2e-13, 0.1] (FP64) or [1e-5, 0.1] (FP32), a forced
+ *   (alpha, sigma) not in the tables, any pixel with l^2 + m^2 >= 1,
+ *   n_rows * n_chan >= 2^32; WG_EUNSUPPORTED when no printed kernel reaches
+ *   epsilon or the grid exceeds the FFT size limit; WG_ENOMEM, WG_EHIP. */
+int wg_plan_create(const wg_plan_desc *desc, wg_plan **out);
+
+/* Destroy a plan and release its device memory (after synchronising the
+ * plan's stream).  NULL is accepted. */
+int wg_plan_destroy(wg_plan *plan);
+
+/* Degridding (forward, eq. R3 with R1, R2): vis = wgt * R(dirty).
+ *   dirty     device [npix_x][npix_y] float32 (WG_F32) or float64 (WG_F64)
+ *   wgt       device [n_rows][n_chan] real of the same precision, or NULL;
+ *             multiplies the output (Appendix B)
+ *   vis       device [n_rows][n_chan] complex (interleaved re, im); fully
+ *             overwritten, masked entries are set to 0
+ *   workspace device scratch of at least wg_workspace_bytes(plan) bytes
+ *   stream    hipStream_t (NULL = default stream); the call is asynchronous.
+ * Errors: WG_EINVAL for NULL plan/dirty/vis or a short workspace; WG_EHIP. */
+int wg_degrid(const wg_plan *plan, const void *dirty, const void *wgt, void *vis,
+              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gridding (adjoint, eqs. Rad1-Rad2): dirty = Re R^H (wgt * vis).
+ *   vis       device [n_rows][n_chan] complex; masked entries are ignored
+ *   wgt       device real [n_rows][n_chan] or NULL; multiplies the input
+ *   dirty     device [npix_x][npix_y] real; fully overwritten
+ * Other arguments and errors as wg_degrid.  Concurrent calls on one plan are
+ * safe when each uses its own workspace and output. */
+int wg_grid(const wg_plan *plan, const void *vis, const void *wgt, void *dirty,
+            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Plan summary (host struct, filled by wg_plan_info). */
+typedef struct {
+    int     alpha;            /* kernel support in cells                             */
+    double  sigma, beta, mu;  /* oversampling and modified-ES parameters (App. A)     */
+    double  eps_kernel;       /* tabulated kernel accuracy eps_k                      */
+    int     poly_degree;      /* degree of the per-cell kernel polynomials            */
+    int     nu, nv;           /* oversampled grid size (u pairs with x)               */
+    int     nw;               /* number of w-planes                                   */
+    double  dw, w0;           /* w-plane spacing and first plane (wavelengths)        */
+    double  wmin, wmax;       /* range of |w| over selected visibilities              */
+    int     npix_x, npix_y;
+    int     precision, do_wgridding;
+    int64_t n_rows, n_chan;
+    int64_t n_vis;            /* selected (unmasked) visibilities                     */
+    int     planes_per_batch; /* w-planes per batch in the apply pipeline             */
+    int     tile;             /* uv tile edge of the index (cells)                    */
+    double  bytes_grid;       /* algorithmic HBM bytes of one wg_grid call            */
+    double  bytes_degrid;     /* algorithmic HBM bytes of one wg_degrid call          */
+    double  predicted_seconds;/* cost-model estimate of one apply                     */
+    size_t  plan_bytes;       /* device bytes held by the plan                        */
+    size_t  index_bytes;      /* of which visibility index                            */
+    size_t  workspace_bytes;  /* per apply call                                       */
+} wg_plan_info_t;
+
+int    wg_plan_info(const wg_plan *plan, wg_plan_info_t *info);
+size_t wg_workspace_bytes(const wg_plan *plan);
+size_t wg_plan_bytes(const wg_plan *plan);
+
+/* Copy the visibility index (sorted order) into caller device buffers:
+ *   keys  [n_vis] uint64: ((t_u * NTv + t_v) * nw + t_w), t_u = i_u/tile,
+ *         t_v = i_v/tile, t_w = first w-plane of the visibility (Sect. 4.3)
+ *   order [n_vis] uint32: linear index r*n_chan + c, ascending within a key.
+ * Either pointer may be NULL.  Asynchronous on ``stream``. */
+int wg_plan_index(const wg_plan *plan, void *keys, void *order, void *stream);
+
+const char *wg_strerror(int code);
+
+/* ---- host-only helpers (no device needed) -------------------------------
+ * These expose pieces of the host planner for inspection and testing. */
+
+/* Smallest N >= ceil(sigma * npix) that is a multiple of the tile edge (16)
+ * and has no prime factor above 7 (Sect. 2: N = ceil(sigma n), rounded up
+ * for the FFT).  Returns N, or WG_EINVAL. */
+int wg_grid_size(double sigma, int npix);
+
+/* Modified-ES parameters of a printed Appendix-A row.  Returns WG_EINVAL when
+ * (alpha, sigma) is not a printed row. */
+int wg_kernel_params(int alpha, double sigma, double *eps_k, double *beta, double *mu);
+
+/* Kernel choice for a problem (Sect. 4.1): for each support the smallest
+ * printed sigma with factor * eps_k <= epsilon (factor 3 with w-gridding,
+ * 2 without), then the least predicted cost.  n_vis and the |w| range drive
+ * the cost model.  Returns WG_OK, WG_EINVAL or WG_EUNSUPPORTED. */
+int wg_select_kernel(double epsilon, int precision, int do_wgridding, int npix_x, int npix_y,
+                     double pixsize_x, double pixsize_y, int64_t n_vis, double wmin,
+                     double wmax, int *alpha, double *sigma);
+
+/* Piecewise-polynomial kernel (Sect. 4.2): for cell i (0 <= i < alpha) and
+ * z in [-1, 1] the kernel at t = -alpha/2 + i + (z + 1)/2 is
+ * sum_d coeffs[i*(degree+1) + d] * z^d.  Fills at most cap doubles;
+ * *degree receives the degree.  Interpolation at Chebyshev roots. */
+int wg_kernel_poly(int alpha, double sigma, int precision, double *coeffs, int cap, int *degree);
+
+/* Fourier transform of the kernel, psi(k) = int phi(t) cos(2 pi k t) dt, at
+ * n points (host arrays). */
+int wg_kernel_psi(int alpha, double sigma, const double *k, int n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WGRID_H */

@@ -1,0 +1,13 @@
+"""wgrid for MI355X: the w-gridding radio-interferometry measurement operator of
+Arras et al., "Efficient wide-field radio interferometry response"
+(arXiv:2010.10122), as hand-written HIP kernels behind a C ABI.
+
+    plan = Plan(uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, "f32")
+    vis = plan.degrid(dirty)        # forward operator R  (dirty2ms)
+    img = plan.grid(vis)            # adjoint R^H, real part (ms2dirty)
+"""
+from ._lib import WgridError, WG_F32, WG_F64  # noqa: F401
+from .plan import Plan, grid_size, kernel_params, kernel_poly, kernel_psi, select_kernel  # noqa: F401
+
+__all__ = ["Plan", "WgridError", "WG_F32", "WG_F64", "grid_size", "kernel_params", "kernel_poly",
+           "kernel_psi", "select_kernel"]

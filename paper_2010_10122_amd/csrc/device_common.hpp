@@ -1,0 +1,131 @@
+// Device-side building blocks shared by the wgrid kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace wg {
+
+// ---- complex helpers on HIP's vector types (re in .x, im in .y) ----------
+template <typename R> struct CplxOf;
+template <> struct CplxOf<float> { using T = float2; };
+template <> struct CplxOf<double> { using T = double2; };
+template <typename R> using Cx = typename CplxOf<R>::T;
+
+template <typename C> __device__ __forceinline__ C cmake(decltype(C{}.x) re, decltype(C{}.x) im) {
+    C c;
+    c.x = re;
+    c.y = im;
+    return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return cmake<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cmulconj(C a, C b) {   // a * conj(b)
+    return cmake<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename C, typename R> __device__ __forceinline__ C cscale(C a, R s) {
+    return cmake<C>(a.x * s, a.y * s);
+}
+// multiply by +i (dir = +1) or -i (dir = -1)
+template <int DIR, typename C> __device__ __forceinline__ C cmul_i(C a) {
+    return DIR > 0 ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
+}
+
+constexpr double kC = 299792458.0;          // speed of light, m/s
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ---- geometry of a plan, passed by value to kernels ----------------------
+struct Geom {
+    int nu, nv;          // oversampled grid
+    int ntu, ntv;        // tiles per axis (nu / 16, nv / 16)
+    int nw;              // w-planes
+    int npix_x, npix_y;
+    int alpha;
+    int do_w;
+    double half;         // alpha / 2
+    double pixsize_x, pixsize_y;
+    double w0, dw;
+    int64_t n_chan;
+};
+
+// Per-visibility coordinates in the fixed FP64 operation order of the
+// binning specification: effective coordinates (Sect. 2), Hermitian fold
+// to w >= 0 (eq. Hermitian-symmetry), wrap of u*dl into [0, 1) (the chi of
+// eq. nfft), grid coordinates in cells and the first touched cell/plane.
+// Every operation is rounded on its own (no contraction), so that keys
+// computed here and again by the apply kernels agree bit for bit.
+struct VisCoord {
+    double gu, gv, xw;   // grid coordinates (cells, cells, planes)
+    double ou, ov, ow;   // (first cell) - coordinate, in [-alpha/2, -alpha/2 + 1)
+    int iu, iv;          // first touched cell, wrapped into [0, N)
+    int iw;              // first touched w-plane
+    bool flip;           // fold applied: conjugate the visibility
+};
+
+__device__ __forceinline__ VisCoord vis_coord(double u_m, double v_m, double w_m, double scale,
+                                              const Geom &g) {
+#pragma clang fp contract(off)
+    VisCoord c;
+    double uu = u_m * scale;
+    double vv = v_m * scale;
+    double ww = g.do_w ? w_m * scale : 0.0;
+    c.flip = ww < 0.0;
+    if (c.flip) {
+        uu = -uu;
+        vv = -vv;
+        ww = -ww;
+    }
+    double xu = uu * g.pixsize_x;
+    double xv = vv * g.pixsize_y;
+    double fu = xu - floor(xu);
+    double fv = xv - floor(xv);
+    c.gu = fu * (double)g.nu;
+    c.gv = fv * (double)g.nv;
+    double cu = ceil(c.gu - g.half);
+    double cv = ceil(c.gv - g.half);
+    c.ou = cu - c.gu;
+    c.ov = cv - c.gv;
+    int iu = (int)cu, iv = (int)cv;
+    c.iu = iu < 0 ? iu + g.nu : iu;
+    c.iv = iv < 0 ? iv + g.nv : iv;
+    if (g.do_w) {
+        c.xw = (ww - g.w0) / g.dw;
+        double cw = ceil(c.xw - g.half);
+        c.ow = cw - c.xw;
+        c.iw = (int)cw;
+    } else {
+        c.xw = 0.0;
+        c.ow = 0.0;
+        c.iw = 0;
+    }
+    return c;
+}
+
+// Kernel values at the alpha cells of one axis from the piecewise
+// polynomials of Sect. 4.2: every cell shares the local variable
+// z = 2 (offset + alpha/2) - 1 in [-1, 1), and cell i uses its own
+// coefficients.  coef is degree-major: coef[d * ALPHA + i].
+template <int ALPHA, typename R>
+__device__ __forceinline__ void kernel_values(double offset, double half, const R *__restrict__ coef,
+                                              int degree, R out[ALPHA]) {
+    const R z = (R)(2.0 * (offset + half) - 1.0);
+#pragma unroll
+    for (int i = 0; i < ALPHA; ++i) out[i] = coef[degree * ALPHA + i];
+    for (int d = degree - 1; d >= 0; --d) {
+#pragma unroll
+        for (int i = 0; i < ALPHA; ++i) out[i] = out[i] * z + coef[d * ALPHA + i];
+    }
+}
+
+// blockIdx -> work-item remap that keeps neighbouring tiles on one XCD:
+// workgroups are dealt round-robin over the 8 XCDs, so give XCD x the
+// contiguous range [x * per, (x + 1) * per).  Returns -1 for padding blocks.
+__device__ __forceinline__ int xcd_remap(int bid, int nitems) {
+    const int per = (nitems + 7) / 8;
+    int item = (bid % 8) * per + bid / 8;
+    return item < nitems ? item : -1;
+}
+
+}  // namespace wg

@@ -1,0 +1,394 @@
+// Apply-time kernels: LDS-tiled gridder, gather degridder, the two FFT
+// passes of each direction with the w-screens fused in, and the image-side
+// correction/finalisation kernels.
+#pragma once
+#include "device_common.hpp"
+#include "fft_lds.hpp"
+
+namespace wg {
+
+constexpr int kTileCells = 16;            // uv tile edge (cells)
+constexpr int kTileArea = kTileCells * kTileCells;
+
+// Arguments shared by the gridder and the degridder.
+template <typename R> struct VisArgs {
+    const double *uvw;          // [n_rows][3]
+    const double *scale;        // [n_chan] freq / c
+    const Cx<R> *vis;           // gridder input  [n_rows][n_chan]
+    const R *wgt;               // optional [n_rows][n_chan]
+    const uint32_t *order;      // sorted visibility order
+    const uint32_t *tab_lo;     // [tiles][NJ+1], shift alpha-1
+    const uint32_t *tab_hi;     // [tiles][NJ+1], shift 0
+    const R *coef;              // [degree+1][alpha] kernel polynomial
+    int degree;
+    int P;                      // planes per batch
+    int NJ;                     // batches
+    Geom g;
+};
+
+// ---------------------------------------------------------------------------
+// Gridder (adjoint, eq. Rad2 before the FFT).  One workgroup owns one 16x16
+// tile of the grid for the P planes of batch J and accumulates in LDS every
+// visibility whose kernel footprint reaches the tile: those anchored in the
+// tile itself and in the three neighbouring tiles up/left (a footprint spans
+// at most alpha <= 16 cells).  No two workgroups write the same grid cell,
+// so the tile is flushed with plain coalesced stores, zeros included.
+// ---------------------------------------------------------------------------
+template <typename R, int ALPHA>
+__global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__restrict__ G) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *acc_re = reinterpret_cast<R *>(smem_raw);
+    R *acc_im = acc_re + a.P * kTileArea;
+    const Geom &g = a.g;
+    const int ntiles = g.ntu * g.ntv;
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    if (tile < 0) return;
+    const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < a.P * kTileArea; e += blockDim.x) {
+        acc_re[e] = (R)0;
+        acc_im[e] = (R)0;
+    }
+    __syncthreads();
+    const int j_lo = J * a.P;
+    const int j_hi = min(j_lo + a.P, g.nw);
+    for (int nb = 0; nb < 4; ++nb) {
+        int tu = A - 1 + (nb >> 1);
+        int tv = B - 1 + (nb & 1);
+        if (tu < 0) tu += g.ntu;
+        if (tv < 0) tv += g.ntv;
+        const int64_t bin = (int64_t)tu * g.ntv + tv;
+        const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
+        const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
+        for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
+            const uint32_t idx = a.order[s];
+            const int64_t r = idx / g.n_chan;
+            const int64_t c = idx - r * g.n_chan;
+            const VisCoord vc = vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
+            int la0 = vc.iu - A * kTileCells;
+            int lb0 = vc.iv - B * kTileCells;
+            if (la0 > g.nu / 2) la0 -= g.nu;
+            if (lb0 > g.nv / 2) lb0 -= g.nv;
+            C d = a.vis[idx];
+            if (a.wgt) d = cscale(d, a.wgt[idx]);
+            if (vc.flip) d.y = -d.y;
+            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+            kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
+            kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+            if (g.do_w) {
+                kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+            } else {
+#pragma unroll
+                for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
+            }
+            const int nplanes_vis = g.do_w ? ALPHA : 1;
+#pragma unroll
+            for (int jw = 0; jw < ALPHA; ++jw) {
+                const int j = vc.iw + jw;
+                if (jw >= nplanes_vis || j < j_lo || j >= j_hi) continue;
+                const C dj = cscale(d, kw[jw]);
+                R *pre = acc_re + (j - j_lo) * kTileArea;
+                R *pim = acc_im + (j - j_lo) * kTileArea;
+#pragma unroll
+                for (int i = 0; i < ALPHA; ++i) {
+                    const int la = la0 + i;
+                    if (la < 0 || la >= kTileCells) continue;
+                    const R fr = dj.x * ku[i], fi = dj.y * ku[i];
+#pragma unroll
+                    for (int k = 0; k < ALPHA; ++k) {
+                        const int lb = lb0 + k;
+                        if (lb < 0 || lb >= kTileCells) continue;
+                        atomicAdd(&pre[la * kTileCells + lb], fr * kv[k]);
+                        atomicAdd(&pim[la * kTileCells + lb], fi * kv[k]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int np = j_hi - j_lo;
+    for (int e = tid; e < np * kTileArea; e += blockDim.x) {
+        const int p = e / kTileArea, cell = e - p * kTileArea;
+        const int la = cell / kTileCells, lb = cell - la * kTileCells;
+        const int64_t off = ((int64_t)p * g.nu + (A * kTileCells + la)) * g.nv + (B * kTileCells + lb);
+        G[off] = cmake<C>(acc_re[e], acc_im[e]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Degridder (forward, bracket of eq. R3).  One workgroup per 16x16 tile and
+// batch: the tile plus its (alpha-1)-cell halo of the P planes is staged in
+// LDS, then each thread gathers alpha x alpha x (planes in batch) values for
+// its visibilities and adds the batch's partial sum to its accumulator.
+// ---------------------------------------------------------------------------
+template <typename R, int ALPHA>
+__global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, const Cx<R> *__restrict__ G,
+                                                Cx<R> *__restrict__ visacc) {
+    using C = Cx<R>;
+    constexpr int W = kTileCells + ALPHA - 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *st = reinterpret_cast<C *>(smem_raw);
+    const Geom &g = a.g;
+    const int ntiles = g.ntu * g.ntv;
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    if (tile < 0) return;
+    const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
+    const int64_t bin = tile;
+    const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
+    const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
+    if (s0 >= s1) return;
+    const int tid = threadIdx.x;
+    const int j_lo = J * a.P;
+    const int j_hi = min(j_lo + a.P, g.nw);
+    const int np = j_hi - j_lo;
+    for (int e = tid; e < np * W * W; e += blockDim.x) {
+        const int p = e / (W * W), cell = e - p * (W * W);
+        const int ra = cell / W, rb = cell - ra * W;
+        int ga = A * kTileCells + ra;
+        int gb = B * kTileCells + rb;
+        if (ga >= g.nu) ga -= g.nu;
+        if (gb >= g.nv) gb -= g.nv;
+        st[e] = G[((int64_t)p * g.nu + ga) * g.nv + gb];
+    }
+    __syncthreads();
+    for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
+        const uint32_t idx = a.order[s];
+        const int64_t r = idx / g.n_chan;
+        const int64_t c = idx - r * g.n_chan;
+        const VisCoord vc = vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
+        const int la0 = vc.iu - A * kTileCells;   // in [0, 16) by the index
+        const int lb0 = vc.iv - B * kTileCells;
+        if (la0 < 0 || la0 >= kTileCells || lb0 < 0 || lb0 >= kTileCells) continue;
+        R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+        kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
+        kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+        if (g.do_w) {
+            kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+        } else {
+#pragma unroll
+            for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
+        }
+        const int nplanes_vis = g.do_w ? ALPHA : 1;
+        R sre = 0, sim = 0;
+#pragma unroll
+        for (int jw = 0; jw < ALPHA; ++jw) {
+            const int j = vc.iw + jw;
+            if (jw >= nplanes_vis || j < j_lo || j >= j_hi) continue;
+            const C *pl = st + (j - j_lo) * (W * W) + la0 * W + lb0;
+            R pre = 0, pim = 0;
+#pragma unroll
+            for (int i = 0; i < ALPHA; ++i) {
+                R rre = 0, rim = 0;
+#pragma unroll
+                for (int k = 0; k < ALPHA; ++k) {
+                    const C v = pl[i * W + k];
+                    rre += kv[k] * v.x;
+                    rim += kv[k] * v.y;
+                }
+                pre += ku[i] * rre;
+                pim += ku[i] * rim;
+            }
+            sre += kw[jw] * pre;
+            sim += kw[jw] * pim;
+        }
+        C old = visacc[s];
+        visacc[s] = cmake<C>(old.x + sre, old.y + sim);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FFT passes.  Grid order: rows (contiguous, along v) then columns (along u).
+// ---------------------------------------------------------------------------
+struct PassGeom {
+    int nu, nv, npix_x, npix_y;
+    int P, nw;
+    int do_w;
+    double w0, dw;
+};
+
+// Gridding pass 1: row a of plane p: T[p][a][q] = sum_b G[p][a][b] e^{+2 pi i b q'/N_v}
+// for the npix_y retained q (q' = q - npix_y/2), i.e. the pruned output.
+template <typename R, int NTH>
+__global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, Cx<R> *__restrict__ T,
+                                                   PassGeom pg, FftDesc fd, const Cx<R> *__restrict__ tw) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int a = blockIdx.x, p = blockIdx.y;
+    const C *src = G + ((int64_t)p * pg.nu + a) * pg.nv;
+    for (int e = threadIdx.x; e < pg.nv; e += NTH) buf[e] = src[e];
+    __syncthreads();
+    lds_fft<+1>(buf, 1, fd, tw, threadIdx.x, NTH);
+    C *dst = T + ((int64_t)p * pg.nu + a) * pg.npix_y;
+    const int h = pg.npix_y / 2;
+    for (int q = threadIdx.x; q < pg.npix_y; q += NTH) {
+        int b = q - h;
+        if (b < 0) b += pg.nv;
+        dst[q] = buf[b];
+    }
+}
+
+// Gridding pass 2: K columns q of every plane in the batch, transform along
+// u, keep the npix_x retained p, multiply by the conjugate w-screen
+// exp(-2 pi i c_j (n - 1)) (eq. Rad1, phase reduced in FP64) and add the
+// real part into the image accumulator (owned by this workgroup).
+template <typename R, int NTH>
+__global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, R *__restrict__ acc,
+                                                   const double *__restrict__ nm1, PassGeom pg, int K,
+                                                   int j_lo, int np, FftDesc fd,
+                                                   const Cx<R> *__restrict__ tw) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int q0 = blockIdx.x * K;
+    const int kk = min(K, pg.npix_y - q0);
+    const int h = pg.npix_x / 2;
+    for (int p = 0; p < np; ++p) {
+        const C *src = T + (int64_t)p * pg.nu * pg.npix_y;
+        for (int e = threadIdx.x; e < pg.nu * K; e += NTH) {
+            const int a = e / K, col = e - a * K;
+            buf[e] = col < kk ? src[(int64_t)a * pg.npix_y + q0 + col] : cmake<C>((R)0, (R)0);
+        }
+        __syncthreads();
+        lds_fft<+1>(buf, K, fd, tw, threadIdx.x, NTH);
+        const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
+        for (int e = threadIdx.x; e < pg.npix_x * kk; e += NTH) {
+            const int pp = e / kk, col = e - pp * kk;
+            int ga = pp - h;
+            if (ga < 0) ga += pg.nu;
+            const C hv = buf[ga * K + col];
+            const int64_t pix = (int64_t)pp * pg.npix_y + q0 + col;
+            R val;
+            if (pg.do_w) {
+                double ph = cj * nm1[pix];
+                ph -= rint(ph);
+                R sn, cs;
+                if constexpr (sizeof(R) == 4) sincospif((float)(2.0 * ph), &sn, &cs);
+                else sincospi(2.0 * ph, &sn, &cs);
+                val = hv.x * cs + hv.y * sn;      // Re(h * exp(-2 pi i ph))
+            } else {
+                val = hv.x;
+            }
+            acc[pix] += val;
+        }
+        __syncthreads();
+    }
+}
+
+// Degridding pass A: image row p, for every plane of the batch: screened
+// row I~ exp(+2 pi i c_j (n - 1)) (eqs. R1-R2) placed at the wrapped
+// positions of a zero row of length N_v, transformed along v (e^{-2 pi i}).
+// Output T[p][row][b], all N_v columns.
+template <typename R, int NTH>
+__global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil, const double *__restrict__ nm1,
+                                                     Cx<R> *__restrict__ T, PassGeom pg, int j_lo, int np,
+                                                     FftDesc fd, const Cx<R> *__restrict__ tw) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int row = blockIdx.x;
+    const int h = pg.npix_y / 2;
+    const R *irow = itil + (int64_t)row * pg.npix_y;
+    const double *nrow = nm1 + (int64_t)row * pg.npix_y;
+    for (int p = 0; p < np; ++p) {
+        const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
+        for (int b = threadIdx.x; b < pg.nv; b += NTH) {
+            int q = b < pg.nv - h ? b + h : b - (pg.nv - h);   // inverse of b = (q - h) mod N_v
+            C v = cmake<C>((R)0, (R)0);
+            if (q >= 0 && q < pg.npix_y && (b < pg.npix_y - h || b >= pg.nv - h)) {
+                const R x = irow[q];
+                if (pg.do_w) {
+                    double ph = cj * nrow[q];
+                    ph -= rint(ph);
+                    R sn, cs;
+                    if constexpr (sizeof(R) == 4) sincospif((float)(2.0 * ph), &sn, &cs);
+                    else sincospi(2.0 * ph, &sn, &cs);
+                    v = cmake<C>(x * cs, x * sn);
+                } else {
+                    v = cmake<C>(x, (R)0);
+                }
+            }
+            buf[b] = v;
+        }
+        __syncthreads();
+        lds_fft<-1>(buf, 1, fd, tw, threadIdx.x, NTH);
+        C *dst = T + ((int64_t)p * pg.npix_x + row) * pg.nv;
+        for (int b = threadIdx.x; b < pg.nv; b += NTH) dst[b] = buf[b];
+        __syncthreads();
+    }
+}
+
+// Degridding pass B: K grid columns b of plane p: the npix_x rows of T are
+// placed at wrapped u positions of a zero column of length N_u and
+// transformed along u (e^{-2 pi i}); output G[p][a][b] for all a.
+template <typename R, int NTH>
+__global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T, Cx<R> *__restrict__ G,
+                                                     PassGeom pg, int K, FftDesc fd,
+                                                     const Cx<R> *__restrict__ tw) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int b0 = blockIdx.x * K;
+    const int p = blockIdx.y;
+    const int kk = min(K, pg.nv - b0);
+    const int h = pg.npix_x / 2;
+    const C *src = T + (int64_t)p * pg.npix_x * pg.nv;
+    for (int e = threadIdx.x; e < pg.nu * K; e += NTH) {
+        const int a = e / K, col = e - a * K;
+        // a = (pp - h) mod N_u  <=>  pp = a + h (a < npix_x - h) or a - (N_u - h) (a >= N_u - h)
+        int pp = -1;
+        if (a < pg.npix_x - h) pp = a + h;
+        else if (a >= pg.nu - h) pp = a - (pg.nu - h);
+        C v = cmake<C>((R)0, (R)0);
+        if (pp >= 0 && col < kk) v = src[(int64_t)pp * pg.nv + b0 + col];
+        buf[e] = v;
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, K, fd, tw, threadIdx.x, NTH);
+    C *dst = G + (int64_t)p * pg.nu * pg.nv;
+    for (int e = threadIdx.x; e < pg.nu * kk; e += NTH) {
+        const int a = e / kk, col = e - a * kk;
+        dst[(int64_t)a * pg.nv + b0 + col] = buf[a * K + col];
+    }
+}
+
+// ---- image-side elementwise kernels ----------------------------------------
+template <typename R>
+__global__ void k_scale_image(const R *__restrict__ in, const double *__restrict__ corr, R *__restrict__ out,
+                              int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (R)((double)in[e] * corr[e]);
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *__restrict__ p, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = T{};
+}
+
+// Degridding output: undo the fold (conjugate), apply the weights and
+// scatter from sorted order to [n_rows][n_chan].
+template <typename R>
+__global__ void k_degrid_finish(const Cx<R> *__restrict__ visacc, const uint32_t *__restrict__ order,
+                                const double *__restrict__ uvw, const double *__restrict__ scale,
+                                const R *__restrict__ wgt, int64_t n_active, int64_t n_chan, int do_w,
+                                Cx<R> *__restrict__ vis) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = order[s];
+        const int64_t r = idx / n_chan, c = idx - (idx / n_chan) * n_chan;
+        Cx<R> v = visacc[s];
+        if (do_w && uvw[3 * r + 2] * scale[c] < 0.0) v.y = -v.y;
+        if (wgt) v = cscale(v, wgt[idx]);
+        vis[idx] = v;
+    }
+}
+
+template <typename R>
+__global__ void k_zero_masked(const uint8_t *__restrict__ mask, int64_t n, Cx<R> *__restrict__ vis) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        if (!mask[e]) vis[e] = Cx<R>{};
+}
+
+}  // namespace wg

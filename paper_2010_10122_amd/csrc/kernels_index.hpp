@@ -1,0 +1,232 @@
+// Plan-time kernels: w range, visibility binning keys (Sect. 4.3), stable
+// LSD radix sort, per-(tile, batch) range tables, correction factors.
+#pragma once
+#include "device_common.hpp"
+
+namespace wg {
+
+// ---- w range and active count over selected visibilities -----------------
+// |w| after the fold is non-negative, so its IEEE bit pattern orders like an
+// unsigned integer and integer atomics give exact min/max.
+__global__ void k_wrange(const double *__restrict__ uvw, const double *__restrict__ scale,
+                         const uint8_t *__restrict__ mask, int64_t n_rows, int64_t n_chan,
+                         int do_w, unsigned long long *out /* [0]=min bits, [1]=max bits, [2]=count */) {
+    unsigned long long mn = ~0ull, mx = 0ull, cnt = 0ull;
+    const int64_t n = n_rows * n_chan;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (mask && !mask[k]) continue;
+        ++cnt;
+        if (do_w) {
+            int64_t r = k / n_chan;
+            int64_t c = k - r * n_chan;
+            double w = fabs(uvw[3 * r + 2] * scale[c]);
+            unsigned long long b = (unsigned long long)__double_as_longlong(w);
+            mn = b < mn ? b : mn;
+            mx = b > mx ? b : mx;
+        }
+    }
+    // wave reduction then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long omn = __shfl_down(mn, off, 64);
+        unsigned long long omx = __shfl_down(mx, off, 64);
+        unsigned long long oc = __shfl_down(cnt, off, 64);
+        mn = omn < mn ? omn : mn;
+        mx = omx > mx ? omx : mx;
+        cnt += oc;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&out[0], mn);
+        atomicMax(&out[1], mx);
+        atomicAdd(&out[2], cnt);
+    }
+}
+
+// ---- binning keys: ((t_u * NTv + t_v) * N_w + t_w), masked -> sentinel ----
+__global__ void k_keys(const double *__restrict__ uvw, const double *__restrict__ scale,
+                       const uint8_t *__restrict__ mask, int64_t n_rows, Geom g,
+                       unsigned long long sentinel, unsigned long long *__restrict__ keys,
+                       uint32_t *__restrict__ vals) {
+    const int64_t n = n_rows * g.n_chan;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long key = sentinel;
+        if (!mask || mask[k]) {
+            int64_t r = k / g.n_chan;
+            int64_t c = k - r * g.n_chan;
+            VisCoord vc = vis_coord(uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], scale[c], g);
+            unsigned long long tile = (unsigned long long)(vc.iu >> 4) * (unsigned long long)g.ntv +
+                                      (unsigned long long)(vc.iv >> 4);
+            key = tile * (unsigned long long)g.nw + (unsigned long long)vc.iw;
+        }
+        keys[k] = key;
+        vals[k] = (uint32_t)k;
+    }
+}
+
+// ---- stable LSD radix sort, 8-bit digits ----------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const unsigned long long *__restrict__ keys,
+                                                        int64_t n, int shift, uint32_t *__restrict__ hist,
+                                                        int nblocks) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int i = 0; i < kRsItems; ++i) {
+        int64_t idx = base + i * kRsThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of a uint32 array in tiles of 4096; writes each tile's total.
+constexpr int kScanThreads = 1024;
+constexpr int kScanTile = 4 * kScanThreads;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restrict__ data, int64_t n,
+                                                             uint32_t *__restrict__ tile_sums) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+    uint32_t v[4];
+    uint32_t tsum = 0;
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < n) ? data[base + i] : 0u;
+        tsum += v[i];
+    }
+    // inclusive scan of per-thread sums within the wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = tsum;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t s = threadIdx.x < kScanThreads / 64 ? wsum[threadIdx.x] : 0u;
+        uint32_t t = s;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t y = __shfl_up(t, off, 64);
+            if ((int)threadIdx.x >= off) t += y;
+        }
+        if (threadIdx.x < kScanThreads / 64) wsum[threadIdx.x] = t - s;   // exclusive
+    }
+    __syncthreads();
+    uint32_t run = wsum[wave] + x - tsum;   // exclusive prefix of this thread
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < n) data[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_sums[blockIdx.x] = wsum[wave] + x;
+}
+
+__global__ void k_scan_add(uint32_t *__restrict__ data, int64_t n, const uint32_t *__restrict__ tile_offs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) data[i] += tile_offs[i / kScanTile];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const unsigned long long *__restrict__ kin, const uint32_t *__restrict__ vin,
+    unsigned long long *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ offs, int nblocks) {
+    __shared__ uint32_t base_off[256];
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kRsThreads / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base_off[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    running[tid] = 0;
+    for (int w = 0; w < kRsThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int i = 0; i < kRsItems; ++i) {
+        int64_t idx = (int64_t)blockIdx.x * kRsTile + i * kRsThreads + tid;
+        bool valid = idx < n;
+        unsigned long long key = valid ? kin[idx] : 0ull;
+        uint32_t val = valid ? vin[idx] : 0u;
+        uint32_t digit = (uint32_t)((key >> shift) & 255u);
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (digit >> b) & 1u;
+            unsigned long long bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = running[digit] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][digit];
+            uint32_t dst = base_off[digit] + pos;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kRsThreads / 64; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---- per-(tile, batch) range tables ----------------------------------------
+// Entry e = tile * (NJ + 1) + J holds the first sorted position whose key is
+// >= tile * N_w + clamp(J * P - shift, 0, N_w).  With shift = 0 the entry at
+// J starts batch J; with shift = alpha - 1 it starts the visibilities whose
+// alpha planes reach into batch J.  Each sorted position fills the entries
+// whose thresholds lie in (key[s-1], key[s]].
+__device__ __forceinline__ unsigned long long tab_count(unsigned long long key, int nw, int P, int NJ,
+                                                        int shift) {
+    unsigned long long tile = key / (unsigned long long)nw;
+    int w = (int)(key - tile * (unsigned long long)nw);
+    int j = (w + shift) / P;
+    if (j > NJ) j = NJ;
+    return tile * (unsigned long long)(NJ + 1) + (unsigned long long)(j + 1);
+}
+
+__global__ void k_fill_tab(const unsigned long long *__restrict__ keys, int64_t n_active, int nw, int P,
+                           int NJ, int shift, unsigned long long total, uint32_t *__restrict__ tab) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s <= n_active;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long lo = s == 0 ? 0ull : tab_count(keys[s - 1], nw, P, NJ, shift);
+        unsigned long long hi = s == n_active ? total : tab_count(keys[s], nw, P, NJ, shift);
+        for (unsigned long long e = lo; e < hi; ++e) tab[e] = (uint32_t)s;
+    }
+}
+
+// ---- n - 1 and the correction 1 / (n Psi) per pixel ------------------------
+// Psi = psi(p'/N_u) psi(q'/N_v) psi((n-1) dw) (Sect. 2), psi by quadrature with
+// precomputed nodes t_i and weights wphi_i = w_i phi(t_i) on [0, alpha/2].
+__global__ void k_corr(int npix_x, int npix_y, double pixsize_x, double pixsize_y, int do_w, double dw,
+                       const double *__restrict__ psix, const double *__restrict__ psiy,
+                       const double *__restrict__ qt, const double *__restrict__ qw, int nq,
+                       double *__restrict__ nm1_out, double *__restrict__ corr_out) {
+    const int64_t npix = (int64_t)npix_x * npix_y;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npix;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int p = (int)(e / npix_y), q = (int)(e - (int64_t)p * npix_y);
+        double l = (double)(p - npix_x / 2) * pixsize_x;
+        double m = (double)(q - npix_y / 2) * pixsize_y;
+        double rho = l * l + m * m;
+        double n = sqrt(1.0 - rho);
+        double nm1 = -rho / (1.0 + n);
+        double psi = psix[p] * psiy[q];
+        if (do_w) {
+            double k = nm1 * dw;
+            double acc = 0.0;
+            for (int i = nq - 1; i >= 0; --i) acc += qw[i] * cos(kTwoPi * k * qt[i]);
+            psi *= 2.0 * acc;
+        }
+        nm1_out[e] = nm1;
+        corr_out[e] = 1.0 / (n * psi);
+    }
+}
+
+}  // namespace wg

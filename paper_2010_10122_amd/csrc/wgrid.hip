@@ -1,0 +1,786 @@
+// wgrid: C-ABI implementation (plan construction and the two apply calls).
+// See include/wgrid.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/wgrid.h"
+#include "host_math.hpp"
+#include "kernels_apply.hpp"
+#include "kernels_index.hpp"
+
+using namespace wg;
+
+namespace {
+
+thread_local std::string g_last_hip;
+
+bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    g_last_hip = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        if (!hip_ok((call), #call)) return WG_EHIP;     \
+    } while (0)
+
+#define LAUNCH_CHECK(what)                                              \
+    do {                                                                \
+        if (!hip_ok(hipGetLastError(), what)) return WG_EHIP;           \
+    } while (0)
+
+// Device allocations of one plan, through the caller's allocator if given.
+struct DevMem {
+    wg_alloc_fn alloc = nullptr;
+    wg_free_fn free = nullptr;
+    void *ctx = nullptr;
+    size_t total = 0;                          // bytes currently held
+    std::unordered_map<void *, size_t> sizes;
+    void *get(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        void *p = nullptr;
+        if (alloc) {
+            p = alloc(ctx, bytes);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        if (p) {
+            total += bytes;
+            sizes[p] = bytes;
+        }
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        auto it = sizes.find(p);
+        if (it != sizes.end()) {
+            total -= it->second;
+            sizes.erase(it);
+        }
+        if (free) free(ctx, p);
+        else (void)hipFree(p);
+    }
+};
+
+int64_t grid_blocks(int64_t n, int threads, int64_t cap = 65536) {
+    int64_t b = (n + threads - 1) / threads;
+    return std::max<int64_t>(1, std::min(b, cap));
+}
+
+void make_fft_desc(int n, FftDesc &d) {
+    d.n = n;
+    d.npass = 0;
+    int m = n;
+    for (int r : {8, 4, 2, 5, 3, 7}) {
+        while (m % r == 0 && d.npass < kFftMaxPass) {
+            d.radix[d.npass++] = r;
+            m /= r;
+        }
+    }
+}
+
+// exp(-2 pi i t / N) with the angle folded into [0, pi/4] so that the library
+// sin/cos see a small, exactly scaled argument.
+void twiddles(int n, std::vector<double> &re, std::vector<double> &im) {
+    re.resize(n);
+    im.resize(n);
+    for (int t = 0; t < n; ++t) {
+        // angle fraction f = t/n of a full turn; use octant symmetry on 8t vs n
+        long long k8 = 8LL * t;
+        int oct = (int)(k8 / n);            // 0..7
+        long long rem = k8 - (long long)oct * n;   // in [0, n)
+        // angle inside the octant, in [0, pi/4)
+        double a = (M_PI / 4.0) * (double)rem / (double)n;
+        double c = std::cos(a), s = std::sin(a);
+        double cr, sr;   // cos and sin of (oct * pi/4 + a)
+        const double r2 = 0.70710678118654752440;
+        switch (oct) {
+            case 0: cr = c; sr = s; break;
+            case 1: cr = r2 * (c - s); sr = r2 * (c + s); break;
+            case 2: cr = -s; sr = c; break;
+            case 3: cr = -r2 * (c + s); sr = r2 * (c - s); break;
+            case 4: cr = -c; sr = -s; break;
+            case 5: cr = -r2 * (c - s); sr = -r2 * (c + s); break;
+            case 6: cr = s; sr = -c; break;
+            default: cr = r2 * (c + s); sr = -r2 * (c - s); break;
+        }
+        re[t] = cr;
+        im[t] = -sr;
+    }
+}
+
+}  // namespace
+
+struct wg_plan {
+    wg_plan_desc desc;
+    DevMem mem;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // kernel
+    int alpha = 0, degree = 0, precision = 0, do_w = 0;
+    double sigma = 0, beta = 0, mu = 0, eps_k = 0;
+    // geometry
+    Geom g{};
+    int P = 1, NJ = 1;
+    int64_t n_total = 0, n_active = 0;
+    double wmin = 0, wmax = 0, predicted = 0;
+    FftDesc fft_u{}, fft_v{};
+    int k_cols = 1;     // columns per workgroup in the strided passes
+    // device arrays
+    double *scale = nullptr;           // [n_chan]
+    void *coef = nullptr;              // [degree+1][alpha] R
+    void *tw_u = nullptr, *tw_v = nullptr;   // complex R
+    double *nm1 = nullptr, *corr = nullptr;  // [npix_x][npix_y]
+    unsigned long long *keys = nullptr;
+    uint32_t *order = nullptr;
+    uint32_t *tab_lo = nullptr, *tab_hi = nullptr;
+    size_t index_bytes = 0;
+    size_t ws_bytes = 0;
+    // workspace layout (byte offsets)
+    size_t off_G = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0;
+};
+
+namespace {
+
+
+template <typename R> int build_plan_tables(wg_plan *p, const std::vector<double> &coefd,
+                                            const std::vector<double> &twu_re, const std::vector<double> &twu_im,
+                                            const std::vector<double> &twv_re, const std::vector<double> &twv_im) {
+    using C = Cx<R>;
+    std::vector<R> cr(coefd.size());
+    for (size_t i = 0; i < coefd.size(); ++i) cr[i] = (R)coefd[i];
+    p->coef = p->mem.get(cr.size() * sizeof(R));
+    if (!p->coef) return WG_ENOMEM;
+    HIP_TRY(hipMemcpy(p->coef, cr.data(), cr.size() * sizeof(R), hipMemcpyHostToDevice));
+    std::vector<C> tu(twu_re.size()), tv(twv_re.size());
+    for (size_t i = 0; i < tu.size(); ++i) { tu[i].x = (R)twu_re[i]; tu[i].y = (R)twu_im[i]; }
+    for (size_t i = 0; i < tv.size(); ++i) { tv[i].x = (R)twv_re[i]; tv[i].y = (R)twv_im[i]; }
+    p->tw_u = p->mem.get(tu.size() * sizeof(C));
+    p->tw_v = p->mem.get(tv.size() * sizeof(C));
+    if (!p->tw_u || !p->tw_v) return WG_ENOMEM;
+    HIP_TRY(hipMemcpy(p->tw_u, tu.data(), tu.size() * sizeof(C), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->tw_v, tv.data(), tv.size() * sizeof(C), hipMemcpyHostToDevice));
+    return WG_OK;
+}
+
+// Stable LSD radix sort of (keys, vals) on the low `bits` bits.
+// The sorted result is left in (keys, vals); scratch is released before return.
+int radix_sort(wg_plan *p, unsigned long long *const keys_io, uint32_t *const vals_io, int64_t n, int bits,
+               hipStream_t st) {
+    if (n <= 1) return WG_OK;
+    unsigned long long *keys = keys_io;
+    uint32_t *vals = vals_io;
+    const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
+    const int64_t hist_n = 256LL * nblocks;
+    unsigned long long *k2 = (unsigned long long *)p->mem.get(n * sizeof(unsigned long long));
+    uint32_t *v2 = (uint32_t *)p->mem.get(n * sizeof(uint32_t));
+    uint32_t *hist = (uint32_t *)p->mem.get(hist_n * sizeof(uint32_t));
+    // scan scratch: one level of tile sums per recursion level
+    std::vector<int64_t> lens;
+    std::vector<uint32_t *> levels;
+    int64_t len = hist_n;
+    bool ok = k2 && v2 && hist;
+    while (ok && len > 1) {
+        int64_t nt = (len + kScanTile - 1) / kScanTile;
+        uint32_t *buf = (uint32_t *)p->mem.get(std::max<int64_t>(nt, 1) * sizeof(uint32_t));
+        if (!buf) { ok = false; break; }
+        levels.push_back(buf);
+        lens.push_back(len);
+        len = nt;
+        if (nt == 1) break;
+    }
+    int rc = ok ? WG_OK : WG_ENOMEM;
+    for (int shift = 0; rc == WG_OK && shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kRsThreads), 0, st, keys, n, shift, hist, nblocks);
+        // multi-level exclusive scan of hist
+        uint32_t *data = hist;
+        for (size_t lv = 0; lv < levels.size(); ++lv) {
+            int64_t ln = lens[lv];
+            int64_t nt = (ln + kScanTile - 1) / kScanTile;
+            hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanThreads), 0, st, data, ln, levels[lv]);
+            data = levels[lv];
+        }
+        for (size_t lv = levels.size(); lv-- > 0;) {
+            uint32_t *below = lv == 0 ? hist : levels[lv - 1];
+            int64_t ln = lens[lv];
+            if ((ln + kScanTile - 1) / kScanTile > 1)
+                hipLaunchKernelGGL(k_scan_add, dim3((unsigned)grid_blocks(ln, 256, 1LL << 30)), dim3(256), 0, st,
+                                   below, ln, levels[lv]);
+        }
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, st, keys, vals, k2, v2, n, shift,
+                           hist, nblocks);
+        if (!hip_ok(hipGetLastError(), "radix sort")) rc = WG_EHIP;
+        std::swap(keys, k2);
+        std::swap(vals, v2);
+    }
+    if (rc == WG_OK && keys != keys_io) {   // odd pass count: copy back
+        if (!hip_ok(hipMemcpyAsync(keys_io, keys, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st),
+                    "radix sort copy") ||
+            !hip_ok(hipMemcpyAsync(vals_io, vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st),
+                    "radix sort copy"))
+            rc = WG_EHIP;
+        std::swap(keys, k2);
+        std::swap(vals, v2);
+    }
+    if (rc == WG_OK && !hip_ok(hipStreamSynchronize(st), "radix sort sync")) rc = WG_EHIP;
+    p->mem.put(k2 == keys_io ? keys : k2);
+    p->mem.put(v2 == vals_io ? vals : v2);
+    p->mem.put(hist);
+    for (uint32_t *b : levels) p->mem.put(b);
+    return rc;
+}
+
+int validate(const wg_plan_desc *d) {
+    if (!d) return WG_EINVAL;
+    if (d->n_rows < 0 || d->n_chan < 1) return WG_EINVAL;
+    if ((d->n_rows > 0 && !d->uvw) || !d->freq) return WG_EINVAL;
+    if ((unsigned long long)d->n_rows * (unsigned long long)d->n_chan >= (1ULL << 32)) return WG_EINVAL;
+    if (d->npix_x < 32 || d->npix_y < 32 || (d->npix_x & 1) || (d->npix_y & 1)) return WG_EINVAL;
+    if (!(d->pixsize_x > 0.0) || !(d->pixsize_y > 0.0)) return WG_EINVAL;
+    if (d->precision != WG_F32 && d->precision != WG_F64) return WG_EINVAL;
+    if (!(d->epsilon <= 0.1)) return WG_EINVAL;
+    if (d->precision == WG_F32 && !(d->epsilon >= 1e-5)) return WG_EINVAL;
+    if (d->precision == WG_F64 && !(d->epsilon > 2e-13)) return WG_EINVAL;
+    if ((d->alloc == nullptr) != (d->free == nullptr)) return WG_EINVAL;
+    if (d->alpha != 0 || d->sigma != 0.0) {
+        if (!find_row(d->alpha, d->sigma)) return WG_EINVAL;
+    }
+    if (d->planes_per_batch < 0) return WG_EINVAL;
+    double l = (double)(0 - d->npix_x / 2) * d->pixsize_x;
+    double m = (double)(0 - d->npix_y / 2) * d->pixsize_y;
+    if (!(l * l + m * m < 1.0)) return WG_EINVAL;
+    return WG_OK;
+}
+
+int plan_build(wg_plan *p) {
+    const wg_plan_desc &d = p->desc;
+    hipStream_t st = p->stream;
+    HIP_TRY(hipGetDevice(&p->device));
+    p->precision = d.precision;
+    p->do_w = d.do_wgridding ? 1 : 0;
+    p->n_total = d.n_rows * d.n_chan;
+    // channel scale freq / c on the host (same IEEE division as everywhere)
+    std::vector<double> freq(d.n_chan), scale(d.n_chan);
+    HIP_TRY(hipMemcpyAsync(freq.data(), d.freq, d.n_chan * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < d.n_chan; ++c) {
+        if (!(freq[c] > 0.0)) return WG_EINVAL;
+        scale[c] = freq[c] / kC;
+    }
+    p->scale = (double *)p->mem.get(d.n_chan * sizeof(double));
+    if (!p->scale) return WG_ENOMEM;
+    HIP_TRY(hipMemcpy(p->scale, scale.data(), d.n_chan * sizeof(double), hipMemcpyHostToDevice));
+
+    // w range and number of selected visibilities
+    unsigned long long *red = (unsigned long long *)p->mem.get(3 * sizeof(unsigned long long));
+    if (!red) return WG_ENOMEM;
+    unsigned long long init[3] = {~0ull, 0ull, 0ull};
+    HIP_TRY(hipMemcpyAsync(red, init, sizeof(init), hipMemcpyHostToDevice, st));
+    if (p->n_total > 0)
+        hipLaunchKernelGGL(k_wrange, dim3((unsigned)grid_blocks(p->n_total, 256, 4096)), dim3(256), 0, st, d.uvw,
+                           p->scale, d.mask, d.n_rows, d.n_chan, p->do_w, red);
+    LAUNCH_CHECK("k_wrange");
+    unsigned long long hred[3];
+    HIP_TRY(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->mem.put(red);
+    p->n_active = (int64_t)hred[2];
+    if (p->do_w && p->n_active > 0) {
+        std::memcpy(&p->wmin, &hred[0], sizeof(double));
+        std::memcpy(&p->wmax, &hred[1], sizeof(double));
+    } else {
+        p->wmin = p->wmax = 0.0;
+    }
+
+    // kernel choice
+    if (d.alpha) {
+        p->alpha = d.alpha;
+        p->sigma = d.sigma;
+        p->predicted = predict_seconds(d.alpha, d.sigma, d.precision, p->do_w, d.npix_x, d.npix_y,
+                                       max_abs_nm1(d.npix_x, d.npix_y, d.pixsize_x, d.pixsize_y),
+                                       p->n_active, p->wmin, p->wmax);
+    } else if (select_kernel(d.epsilon, d.precision, p->do_w, d.npix_x, d.npix_y, d.pixsize_x, d.pixsize_y,
+                             p->n_active, p->wmin, p->wmax, &p->alpha, &p->sigma, &p->predicted) != 0) {
+        return WG_EUNSUPPORTED;
+    }
+    const KernelRow *row = find_row(p->alpha, p->sigma);
+    p->beta = row->beta;
+    p->mu = row->mu;
+    p->eps_k = row->eps;
+    p->degree = choose_degree(p->alpha, p->beta, p->mu, p->eps_k, d.precision);
+
+    // geometry (Sect. 2)
+    Geom &g = p->g;
+    g.nu = grid_size(p->sigma, d.npix_x);
+    g.nv = grid_size(p->sigma, d.npix_y);
+    g.ntu = g.nu / kTile;
+    g.ntv = g.nv / kTile;
+    g.npix_x = d.npix_x;
+    g.npix_y = d.npix_y;
+    g.alpha = p->alpha;
+    g.do_w = p->do_w;
+    g.half = 0.5 * p->alpha;
+    g.pixsize_x = d.pixsize_x;
+    g.pixsize_y = d.pixsize_y;
+    g.n_chan = d.n_chan;
+    if (p->do_w) {
+        g.dw = 1.0 / (2.0 * p->sigma * max_abs_nm1(d.npix_x, d.npix_y, d.pixsize_x, d.pixsize_y));
+        g.w0 = p->wmin - g.dw * (p->alpha - 1) * 0.5;
+        g.nw = (int)std::ceil((p->wmax - p->wmin) / g.dw) + p->alpha;
+    } else {
+        g.dw = 1.0;
+        g.w0 = 0.0;
+        g.nw = 1;
+    }
+    const size_t sc = d.precision == WG_F32 ? 8 : 16;
+    const size_t sr = sc / 2;
+    // FFT length limit: one transform line must fit in LDS
+    const size_t lds_cap = 160 * 1024;
+    if ((size_t)std::max(g.nu, g.nv) * sc > lds_cap || std::max(g.nu, g.nv) > max_grid(d.precision))
+        return WG_EUNSUPPORTED;
+    // columns per workgroup in the strided passes: fill up to 96 KB of LDS
+    // (FP32 <= 12288 values = 512 threads x kFftMaxC, FP64 <= 6144 = 256 x kFftMaxC)
+    p->k_cols = 1;
+    while (p->k_cols < 8 && (size_t)g.nu * (2 * p->k_cols) * sc <= 96 * 1024) p->k_cols *= 2;
+    // planes per batch: gridder LDS P * 256 * sc <= 64 KB, degridder staging
+    // P * (16 + alpha - 1)^2 * sc <= 72 KB
+    const int wst = kTileCells + p->alpha - 1;
+    int pmax = (int)std::min<size_t>(64 * 1024 / (kTileArea * sc), 72 * 1024 / ((size_t)wst * wst * sc));
+    pmax = std::max(1, std::min(pmax, 32));
+    p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, pmax) : pmax;
+    p->P = std::min(p->P, g.nw);
+    p->NJ = (g.nw + p->P - 1) / p->P;
+    make_fft_desc(g.nu, p->fft_u);
+    make_fft_desc(g.nv, p->fft_v);
+
+    // host tables: polynomial, psi on the pixel axes, quadrature nodes, twiddles
+    std::vector<double> coef_id;
+    kernel_poly(p->alpha, p->beta, p->mu, p->degree, coef_id);
+    std::vector<double> coefd((size_t)(p->degree + 1) * p->alpha);   // degree-major
+    for (int i = 0; i < p->alpha; ++i)
+        for (int k = 0; k <= p->degree; ++k)
+            coefd[(size_t)k * p->alpha + i] = coef_id[(size_t)i * (p->degree + 1) + k];
+    std::vector<double> qt, qw;
+    psi_nodes(p->alpha, p->beta, p->mu, qt, qw);
+    std::vector<double> psix(d.npix_x), psiy(d.npix_y);
+    for (int i = 0; i < d.npix_x; ++i) psix[i] = psi_eval((double)(i - d.npix_x / 2) / g.nu, qt, qw);
+    for (int i = 0; i < d.npix_y; ++i) psiy[i] = psi_eval((double)(i - d.npix_y / 2) / g.nv, qt, qw);
+    std::vector<double> tur, tui, tvr, tvi;
+    twiddles(g.nu, tur, tui);
+    twiddles(g.nv, tvr, tvi);
+    int rc = d.precision == WG_F32 ? build_plan_tables<float>(p, coefd, tur, tui, tvr, tvi)
+                                   : build_plan_tables<double>(p, coefd, tur, tui, tvr, tvi);
+    if (rc != WG_OK) return rc;
+
+    // correction factors
+    const int64_t npix = (int64_t)d.npix_x * d.npix_y;
+    p->nm1 = (double *)p->mem.get(npix * sizeof(double));
+    p->corr = (double *)p->mem.get(npix * sizeof(double));
+    double *dpx = (double *)p->mem.get(d.npix_x * sizeof(double));
+    double *dpy = (double *)p->mem.get(d.npix_y * sizeof(double));
+    double *dqt = (double *)p->mem.get(qt.size() * sizeof(double));
+    double *dqw = (double *)p->mem.get(qw.size() * sizeof(double));
+    if (!p->nm1 || !p->corr || !dpx || !dpy || !dqt || !dqw) return WG_ENOMEM;
+    HIP_TRY(hipMemcpy(dpx, psix.data(), psix.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dpy, psiy.data(), psiy.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dqt, qt.data(), qt.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dqw, qw.data(), qw.size() * sizeof(double), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_corr, dim3((unsigned)grid_blocks(npix, 256, 1 << 20)), dim3(256), 0, st, d.npix_x,
+                       d.npix_y, d.pixsize_x, d.pixsize_y, p->do_w, g.dw, dpx, dpy, dqt, dqw, (int)qt.size(),
+                       p->nm1, p->corr);
+    LAUNCH_CHECK("k_corr");
+
+    // visibility index: keys, stable sort, batch tables
+    const unsigned long long ntiles = (unsigned long long)g.ntu * g.ntv;
+    const unsigned long long sentinel = ntiles * (unsigned long long)g.nw;
+    int bits = 1;
+    while (bits < 64 && (sentinel >> bits) != 0) ++bits;
+    const int64_t nkeys = std::max<int64_t>(p->n_total, 1);
+    p->keys = (unsigned long long *)p->mem.get(nkeys * sizeof(unsigned long long));
+    p->order = (uint32_t *)p->mem.get(nkeys * sizeof(uint32_t));
+    if (!p->keys || !p->order) return WG_ENOMEM;
+    if (p->n_total > 0) {
+        hipLaunchKernelGGL(k_keys, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 20)), dim3(256), 0, st, d.uvw,
+                           p->scale, d.mask, d.n_rows, g, sentinel, p->keys, p->order);
+        LAUNCH_CHECK("k_keys");
+        rc = radix_sort(p, p->keys, p->order, p->n_total, bits, st);
+        if (rc != WG_OK) return rc;
+    }
+    const unsigned long long tab_n = ntiles * (unsigned long long)(p->NJ + 1);
+    p->tab_lo = (uint32_t *)p->mem.get(tab_n * sizeof(uint32_t));
+    p->tab_hi = (uint32_t *)p->mem.get(tab_n * sizeof(uint32_t));
+    if (!p->tab_lo || !p->tab_hi) return WG_ENOMEM;
+    hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
+                       p->keys, p->n_active, g.nw, p->P, p->NJ, p->alpha - 1, tab_n, p->tab_lo);
+    hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
+                       p->keys, p->n_active, g.nw, p->P, p->NJ, 0, tab_n, p->tab_hi);
+    LAUNCH_CHECK("k_fill_tab");
+    p->index_bytes = nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t);
+    HIP_TRY(hipStreamSynchronize(st));
+    p->mem.put(dpx);
+    p->mem.put(dpy);
+    p->mem.put(dqt);
+    p->mem.put(dqw);
+
+    // workspace layout
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    p->off_G = off;
+    off = align(off + (size_t)p->P * g.nu * g.nv * sc);
+    p->off_T = off;
+    off = align(off + (size_t)p->P * std::max((size_t)g.nu * d.npix_y, (size_t)d.npix_x * g.nv) * sc);
+    p->off_acc = off;
+    off = align(off + (size_t)npix * sr);
+    p->off_itil = off;
+    off = align(off + (size_t)npix * sr);
+    p->off_vacc = off;
+    off = align(off + (size_t)std::max<int64_t>(p->n_active, 1) * sc);
+    p->ws_bytes = off;
+    return WG_OK;
+}
+
+// ---- apply ------------------------------------------------------------------
+
+template <typename R, int ALPHA> struct Launch {
+    static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, hipStream_t st) {
+        const int nt = p->g.ntu * p->g.ntv;
+        const int nb = ((nt + 7) / 8) * 8;
+        const size_t lds = 2 * (size_t)p->P * kTileArea * sizeof(R);
+        hipLaunchKernelGGL((k_grid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G);
+    }
+    static void degrid(const wg_plan *p, const VisArgs<R> &va, int J, const Cx<R> *G, Cx<R> *vacc,
+                       hipStream_t st) {
+        const int nt = p->g.ntu * p->g.ntv;
+        const int nb = ((nt + 7) / 8) * 8;
+        const int W = kTileCells + ALPHA - 1;
+        const size_t lds = (size_t)p->P * W * W * sizeof(Cx<R>);
+        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G, vacc);
+    }
+};
+
+template <typename R>
+void launch_vis_kernel(bool gridding, const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *vacc,
+                       hipStream_t st) {
+    switch (p->alpha) {
+#define CASE(A)                                                              \
+    case A:                                                                  \
+        if (gridding) Launch<R, A>::grid(p, va, J, G, st);                   \
+        else Launch<R, A>::degrid(p, va, J, G, vacc, st);                    \
+        break;
+        CASE(4) CASE(7) CASE(8) CASE(12) CASE(16)
+#undef CASE
+        default: break;
+    }
+}
+
+template <typename R, int NTH> struct FftLaunch {
+    static void rows_grid(const wg_plan *p, const Cx<R> *G, Cx<R> *T, const PassGeom &pg, int np, hipStream_t st) {
+        hipLaunchKernelGGL((k_rows_grid<R, NTH>), dim3(p->g.nu, np), dim3(NTH), p->g.nv * sizeof(Cx<R>), st, G, T,
+                           pg, p->fft_v, (const Cx<R> *)p->tw_v);
+    }
+    static void cols_grid(const wg_plan *p, const Cx<R> *T, R *acc, const PassGeom &pg, int j_lo, int np,
+                          hipStream_t st) {
+        const int K = p->k_cols;
+        const int nb = (p->g.npix_y + K - 1) / K;
+        hipLaunchKernelGGL((k_cols_grid<R, NTH>), dim3(nb), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>), st, T,
+                           acc, p->nm1, pg, K, j_lo, np, p->fft_u, (const Cx<R> *)p->tw_u);
+    }
+    static void rows_degrid(const wg_plan *p, const R *itil, Cx<R> *T, const PassGeom &pg, int j_lo, int np,
+                            hipStream_t st) {
+        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x), dim3(NTH), p->g.nv * sizeof(Cx<R>), st,
+                           itil, p->nm1, T, pg, j_lo, np, p->fft_v, (const Cx<R> *)p->tw_v);
+    }
+    static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
+                            hipStream_t st) {
+        const int K = p->k_cols;
+        const int nb = (p->g.nv + K - 1) / K;
+        hipLaunchKernelGGL((k_cols_degrid<R, NTH>), dim3(nb, np), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>),
+                           st, T, G, pg, K, p->fft_u, (const Cx<R> *)p->tw_u);
+    }
+};
+
+// Row transforms (K = 1, N up to the LDS limit): FP32 256/1024 threads,
+// FP64 256/512.  Column transforms (N * K <= 96 KB of LDS): FP32 256/512,
+// FP64 256.  Each choice keeps a thread at <= kFftMaxC values without spills.
+#define DISPATCH_ROWS(n, EXPR_T)                                       \
+    do {                                                               \
+        if ((n) <= 256 * kFftMaxC) {                                   \
+            constexpr int NTH = 256;                                   \
+            EXPR_T;                                                    \
+        } else {                                                       \
+            constexpr int NTH = sizeof(R) == 4 ? 1024 : 512;           \
+            EXPR_T;                                                    \
+        }                                                              \
+    } while (0)
+#define DISPATCH_COLS(n, EXPR_T)                                       \
+    do {                                                               \
+        if (sizeof(R) == 8 || (n) <= 256 * kFftMaxC) {                 \
+            constexpr int NTH = 256;                                   \
+            EXPR_T;                                                    \
+        } else {                                                       \
+            constexpr int NTH = sizeof(R) == 4 ? 512 : 256;            \
+            EXPR_T;                                                    \
+        }                                                              \
+    } while (0)
+
+template <typename R>
+int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void *out, void *ws, size_t ws_bytes,
+          hipStream_t st) {
+    using C = Cx<R>;
+    if (!ws || ws_bytes < p->ws_bytes) return WG_EINVAL;
+    const Geom &g = p->g;
+    const wg_plan_desc &d = p->desc;
+    unsigned char *w = (unsigned char *)ws;
+    C *G = (C *)(w + p->off_G);
+    C *T = (C *)(w + p->off_T);
+    R *acc = (R *)(w + p->off_acc);
+    R *itil = (R *)(w + p->off_itil);
+    C *vacc = (C *)(w + p->off_vacc);
+    const int64_t npix = (int64_t)g.npix_x * g.npix_y;
+
+    VisArgs<R> va;
+    va.uvw = d.uvw;
+    va.scale = p->scale;
+    va.vis = gridding ? (const C *)in : nullptr;
+    va.wgt = (const R *)wgt;
+    va.order = p->order;
+    va.tab_lo = p->tab_lo;
+    va.tab_hi = p->tab_hi;
+    va.coef = (const R *)p->coef;
+    va.degree = p->degree;
+    va.P = p->P;
+    va.NJ = p->NJ;
+    va.g = g;
+    PassGeom pg{g.nu, g.nv, g.npix_x, g.npix_y, p->P, g.nw, g.do_w, g.w0, g.dw};
+
+    if (gridding) {
+        hipLaunchKernelGGL(k_fill_zero<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st, acc, npix);
+        if (p->n_active > 0) {
+            for (int J = 0; J < p->NJ; ++J) {
+                const int j_lo = J * p->P;
+                const int np = std::min(p->P, g.nw - j_lo);
+                launch_vis_kernel<R>(true, p, va, J, G, nullptr, st);
+                DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_grid(p, G, T, pg, np, st)));
+                DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+            }
+        }
+        hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st, acc,
+                           p->corr, (R *)out, npix);
+    } else {
+        if (p->n_total > 0 && d.mask)
+            hipLaunchKernelGGL(k_zero_masked<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256), 0,
+                               st, d.mask, p->n_total, (C *)out);
+        if (p->n_active > 0) {
+            hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st,
+                               (const R *)in, p->corr, itil, npix);
+            hipLaunchKernelGGL(k_fill_zero<C>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256), 0,
+                               st, vacc, p->n_active);
+            for (int J = 0; J < p->NJ; ++J) {
+                const int j_lo = J * p->P;
+                const int np = std::min(p->P, g.nw - j_lo);
+                DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_degrid(p, itil, T, pg, j_lo, np, st)));
+                DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_degrid(p, T, G, pg, np, st)));
+                launch_vis_kernel<R>(false, p, va, J, G, vacc, st);
+            }
+            hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256), 0,
+                               st, vacc, p->order, d.uvw, p->scale, (const R *)wgt, p->n_active, d.n_chan, g.do_w,
+                               (C *)out);
+        }
+    }
+    if (!hip_ok(hipGetLastError(), gridding ? "wg_grid launch" : "wg_degrid launch")) return WG_EHIP;
+    return WG_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+int wg_plan_create(const wg_plan_desc *desc, wg_plan **out) {
+    if (!out) return WG_EINVAL;
+    *out = nullptr;
+    int rc = validate(desc);
+    if (rc != WG_OK) return rc;
+    wg_plan *p = new (std::nothrow) wg_plan();
+    if (!p) return WG_ENOMEM;
+    p->desc = *desc;
+    p->stream = (hipStream_t)desc->stream;
+    p->mem.alloc = desc->alloc;
+    p->mem.free = desc->free;
+    p->mem.ctx = desc->alloc_ctx;
+    rc = plan_build(p);
+    if (rc != WG_OK) {
+        (void)hipStreamSynchronize(p->stream);
+        wg_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return WG_OK;
+}
+
+int wg_plan_destroy(wg_plan *p) {
+    if (!p) return WG_OK;
+    (void)hipStreamSynchronize(p->stream);
+    p->mem.put(p->scale);
+    p->mem.put(p->coef);
+    p->mem.put(p->tw_u);
+    p->mem.put(p->tw_v);
+    p->mem.put(p->nm1);
+    p->mem.put(p->corr);
+    p->mem.put(p->keys);
+    p->mem.put(p->order);
+    p->mem.put(p->tab_lo);
+    p->mem.put(p->tab_hi);
+    delete p;
+    return WG_OK;
+}
+
+int wg_degrid(const wg_plan *p, const void *dirty, const void *wgt, void *vis, void *workspace,
+              size_t workspace_bytes, void *stream) {
+    if (!p || !dirty || (!vis && p->n_total > 0)) return WG_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return p->precision == WG_F32 ? apply<float>(p, false, dirty, wgt, vis, workspace, workspace_bytes, st)
+                                  : apply<double>(p, false, dirty, wgt, vis, workspace, workspace_bytes, st);
+}
+
+int wg_grid(const wg_plan *p, const void *vis, const void *wgt, void *dirty, void *workspace,
+            size_t workspace_bytes, void *stream) {
+    if (!p || !dirty || (!vis && p->n_total > 0)) return WG_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return p->precision == WG_F32 ? apply<float>(p, true, vis, wgt, dirty, workspace, workspace_bytes, st)
+                                  : apply<double>(p, true, vis, wgt, dirty, workspace, workspace_bytes, st);
+}
+
+int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
+    if (!p || !info) return WG_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    const Geom &g = p->g;
+    info->alpha = p->alpha;
+    info->sigma = p->sigma;
+    info->beta = p->beta;
+    info->mu = p->mu;
+    info->eps_kernel = p->eps_k;
+    info->poly_degree = p->degree;
+    info->nu = g.nu;
+    info->nv = g.nv;
+    info->nw = g.nw;
+    info->dw = g.dw;
+    info->w0 = g.w0;
+    info->wmin = p->wmin;
+    info->wmax = p->wmax;
+    info->npix_x = g.npix_x;
+    info->npix_y = g.npix_y;
+    info->precision = p->precision;
+    info->do_wgridding = p->do_w;
+    info->n_rows = p->desc.n_rows;
+    info->n_chan = p->desc.n_chan;
+    info->n_vis = p->n_active;
+    info->planes_per_batch = p->P;
+    info->tile = kTile;
+    const double sc = p->precision == WG_F32 ? 8.0 : 16.0, sr = sc / 2;
+    const double nvis = (double)p->n_active;
+    const double planes = (double)g.nw * ((double)g.nu * g.nv * sc * 2.0 + (double)g.nu * g.npix_y * sc * 2.0 +
+                                          2.0 * (double)g.npix_x * g.npix_y * sr);
+    const double vis_b = nvis * (sc + 4.0) + (double)p->desc.n_rows * 24.0;
+    info->bytes_grid = planes + vis_b;
+    info->bytes_degrid = planes + vis_b;
+    info->predicted_seconds = p->predicted;
+    info->plan_bytes = p->mem.total;
+    info->index_bytes = p->index_bytes;
+    info->workspace_bytes = p->ws_bytes;
+    return WG_OK;
+}
+
+size_t wg_workspace_bytes(const wg_plan *p) { return p ? p->ws_bytes : 0; }
+size_t wg_plan_bytes(const wg_plan *p) { return p ? p->mem.total : 0; }
+
+int wg_plan_index(const wg_plan *p, void *keys, void *order, void *stream) {
+    if (!p) return WG_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->n_active == 0) return WG_OK;
+    if (keys)
+        HIP_TRY(hipMemcpyAsync(keys, p->keys, p->n_active * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+    if (order)
+        HIP_TRY(hipMemcpyAsync(order, p->order, p->n_active * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    return WG_OK;
+}
+
+const char *wg_strerror(int code) {
+    switch (code) {
+        case WG_OK: return "ok";
+        case WG_EINVAL: return "invalid argument";
+        case WG_ENOMEM: return "out of device memory";
+        case WG_EHIP: {
+            static thread_local std::string s;
+            s = "HIP error: " + g_last_hip;
+            return s.c_str();
+        }
+        case WG_EUNSUPPORTED: return "unsupported request (no printed kernel reaches epsilon, or grid too large)";
+        default: return "unknown error";
+    }
+}
+
+int wg_grid_size(double sigma, int npix) {
+    if (!(sigma > 1.0) || npix < 1) return WG_EINVAL;
+    return grid_size(sigma, npix);
+}
+
+int wg_kernel_params(int alpha, double sigma, double *eps_k, double *beta, double *mu) {
+    const KernelRow *r = find_row(alpha, sigma);
+    if (!r) return WG_EINVAL;
+    if (eps_k) *eps_k = r->eps;
+    if (beta) *beta = r->beta;
+    if (mu) *mu = r->mu;
+    return WG_OK;
+}
+
+int wg_select_kernel(double epsilon, int precision, int do_wgridding, int npix_x, int npix_y, double pixsize_x,
+                     double pixsize_y, int64_t n_vis, double wmin, double wmax, int *alpha, double *sigma) {
+    if (!alpha || !sigma || npix_x < 1 || npix_y < 1 || !(pixsize_x > 0) || !(pixsize_y > 0)) return WG_EINVAL;
+    if (precision != WG_F32 && precision != WG_F64) return WG_EINVAL;
+    if (precision == WG_F32 && !(epsilon >= 1e-5)) return WG_EINVAL;
+    if (precision == WG_F64 && !(epsilon > 2e-13)) return WG_EINVAL;
+    if (select_kernel(epsilon, precision, do_wgridding ? 1 : 0, npix_x, npix_y, pixsize_x, pixsize_y, n_vis, wmin,
+                      wmax, alpha, sigma, nullptr) != 0)
+        return WG_EUNSUPPORTED;
+    return WG_OK;
+}
+
+int wg_kernel_poly(int alpha, double sigma, int precision, double *coeffs, int cap, int *degree) {
+    const KernelRow *r = find_row(alpha, sigma);
+    if (!r || !degree) return WG_EINVAL;
+    int deg = choose_degree(alpha, r->beta, r->mu, r->eps, precision);
+    std::vector<double> c;
+    kernel_poly(alpha, r->beta, r->mu, deg, c);
+    *degree = deg;
+    if (coeffs) {
+        int n = std::min<int>(cap, (int)c.size());
+        for (int i = 0; i < n; ++i) coeffs[i] = c[i];
+    }
+    return WG_OK;
+}
+
+int wg_kernel_psi(int alpha, double sigma, const double *k, int n, double *out) {
+    const KernelRow *r = find_row(alpha, sigma);
+    if (!r || (n > 0 && (!k || !out))) return WG_EINVAL;
+    std::vector<double> qt, qw;
+    psi_nodes(alpha, r->beta, r->mu, qt, qw);
+    for (int i = 0; i < n; ++i) out[i] = psi_eval(k[i], qt, qw);
+    return WG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+* binning and plan geometry: bit-exact against the oracle's binning spec;
+* same plan as O2 (plain gridder, exact kernel): agreement up to the
+  polynomial-kernel and rounding error;
+* against O1 (direct DFT of eq. 3): relative L2 error <= epsilon, both
+  directions, both precisions, with and without w-gridding;
+* adjointness (Sect. 5.1), weights, masks, batch boundaries, empty input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kernel as K
+from oracle import o1, o2
+from oracle import plan as P
+
+from gpu_util import eps_adj, oracle_plan_from, rel, run_product
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_10122_amd  # noqa: F401  (fails loudly without libwgrid.so)
+    return torch.device("cuda:0")
+
+
+def _case_small():
+    return synth.small_plain()
+
+
+def _case_accuracy(npix=256, fov=15.0, nvis=1000, seed=0):
+    return synth.accuracy_setup(seed=seed, npix=npix, fov_deg=fov, nvis=nvis)
+
+
+def _case_multichan(seed=12, nrow=400, nchan=6, npix=128, fov=8.0):
+    rng = np.random.default_rng(seed)
+    ant = synth.antennas_disk(rng, 12, 3000.0)
+    uvw = synth.earth_rotation_uvw(ant, 6.0, nrow // 66 + 1)[:nrow]
+    freq = synth.channels(0.9e9, 1.7e9, nchan)
+    pix = fov * math.pi / 180 / npix
+    return dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+                vis=synth.complex_gaussian(rng, (uvw.shape[0], nchan)),
+                dirty=rng.standard_normal((npix, npix)))
+
+
+# ---------------------------------------------------------------------------
+# binning (integer work: bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["small", "multichan", "masked"])
+def test_binning_and_plan_bit_exact(dev, which):
+    case = _case_small() if which == "small" else _case_multichan()
+    mask = None
+    if which == "masked":
+        mask = (np.random.default_rng(3).random(case["vis"].shape) > 0.3).astype(np.uint8)
+    print(f"[binning] case={which}", flush=True)
+    for prec, eps in (("f64", 1e-10), ("f32", 1e-5)):
+        res = run_product(case, eps, prec, torch, dev, mask=mask)
+        info = res["info"]
+        pl = oracle_plan_from(info, case, mask)
+        assert (info["nu"], info["nv"], info["nw"]) == (pl["nu"], pl["nv"], pl["nw"])
+        assert info["dw"] == pl["dw"] and info["w0"] == pl["w0"]
+        assert info["wmin"] == pl["wmin"] and info["wmax"] == pl["wmax"]
+        assert (info["beta"], info["mu"], info["eps_kernel"]) == (pl["beta"], pl["mu"], pl["eps_k"])
+        b = P.bin_visibilities(case["uvw"], case["freq"], pl, mask)
+        keys, order = res["plan"].index()
+        keys = keys.cpu().numpy().astype(np.uint64)
+        order = order.cpu().numpy().astype(np.int64)
+        assert info["n_vis"] == len(b["idx"])
+        assert np.array_equal(keys, b["key"][b["order"]])
+        assert np.array_equal(order, b["idx"][b["order"]])
+        res["plan"].close()
+
+
+# ---------------------------------------------------------------------------
+# same plan as O2
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,sigma,prec", [(16, 1.35, "f64"), (12, 1.5, "f64"), (8, 1.45, "f32"),
+                                              (7, 1.5, "f32"), (4, 2.0, "f64"), (8, 1.45, "f64")])
+def test_same_plan_as_o2(dev, alpha, sigma, prec):
+    case = _case_small()
+    print(f"[o2] alpha={alpha} sigma={sigma} {prec}", flush=True)
+    res = run_product(case, 1e-2, prec, torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=alpha, sigma=sigma)
+    pl = oracle_plan_from(res["info"], case)
+    d2 = o2.degrid(case["uvw"], case["freq"], case["dirty"], pl)
+    i2 = o2.grid(case["uvw"], case["freq"], case["vis"], pl)
+    # difference = polynomial kernel error (< 0.35 eps_k per value) + rounding
+    tol = max(pl["eps_k"], 1e-13 if prec == "f64" else 3e-6)
+    assert rel(res["vis"], d2) < tol
+    assert rel(res["img"], i2) < tol
+    res["plan"].close()
+
+
+@pytest.mark.parametrize("ppb", [1, 3, 5])
+def test_batch_boundaries(dev, ppb):
+    """Forcing few planes per batch moves visibilities across batch
+    boundaries; the result must not change beyond rounding."""
+    case = _case_small()
+    ref = run_product(case, 1e-10, "f64", torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=12, sigma=1.5)
+    res = run_product(case, 1e-10, "f64", torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=12, sigma=1.5,
+                      planes_per_batch=ppb)
+    assert res["info"]["planes_per_batch"] == ppb
+    assert rel(res["vis"], ref["vis"]) < 1e-13
+    assert rel(res["img"], ref["img"]) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# against the direct DFT (O1): rel L2 <= epsilon
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-10), ("f64", 1e-7), ("f32", 1e-5), ("f32", 1e-4), ("f64", 1e-12)])
+def test_small_plain_vs_direct(dev, prec, eps):
+    case = _case_small()
+    print(f"[o1 small] {prec} eps={eps}", flush=True)
+    res = run_product(case, eps, prec, torch, dev, dirty=case["dirty"], vis=case["vis"])
+    d1 = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"])
+    i1 = o1.adjoint(case["uvw"], case["freq"], case["vis"], 64, 64, case["pixsize_x"], case["pixsize_y"])
+    ev, ei = rel(res["vis"], d1), rel(res["img"], i1)
+    print(f"   plan {res['info']['alpha']}/{res['info']['sigma']}: degrid {ev:.2e} grid {ei:.2e}")
+    assert ev < eps and ei < eps
+    assert K.feasible(res["info"]["alpha"], res["info"]["sigma"], eps, True)
+    res["plan"].close()
+
+
+@pytest.mark.parametrize("prec,eps,do_w", [("f32", 1e-5, True), ("f32", 1e-5, False), ("f64", 1e-9, True),
+                                           ("f64", 1e-12, False)])
+def test_accuracy_setup_vs_direct(dev, prec, eps, do_w):
+    """Sect. 5 set-up (256^2 here), several tiles and a ragged last batch:
+    accuracy of both directions against the direct transform and
+    adjointness (paper: < 1e-7 FP32, < 1e-15 FP64 at its settings)."""
+    case = _case_accuracy()
+    print(f"[o1 accuracy] {prec} eps={eps} w={do_w}", flush=True)
+    res = run_product(case, eps, prec, torch, dev, dirty=case["dirty"], vis=case["vis"], do_wgridding=do_w)
+    n = case["npix_x"]
+    d1 = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"],
+                    do_wgridding=do_w)
+    i1 = o1.adjoint(case["uvw"], case["freq"], case["vis"], n, n, case["pixsize_x"], case["pixsize_y"],
+                    do_wgridding=do_w)
+    ev, ei = rel(res["vis"], d1), rel(res["img"], i1)
+    ea = eps_adj(res["vis"], case["vis"], case["dirty"], res["img"])
+    print(f"   plan {res['info']['alpha']}/{res['info']['sigma']} N={res['info']['nu']} Nw={res['info']['nw']}:"
+          f" degrid {ev:.2e} grid {ei:.2e} adj {ea:.2e}")
+    assert ev < eps and ei < eps
+    assert ea < (1e-6 if prec == "f32" else 1e-12)
+    res["plan"].close()
+
+
+def test_multichannel_weights_mask_vs_direct(dev):
+    case = _case_multichan()
+    rng = np.random.default_rng(21)
+    wgt = rng.uniform(0.5, 1.5, case["vis"].shape)
+    mask = (rng.random(case["vis"].shape) > 0.2).astype(np.uint8)
+    for prec, eps in (("f64", 1e-9), ("f32", 1e-5)):
+        res = run_product(case, eps, prec, torch, dev, dirty=case["dirty"], vis=case["vis"], wgt=wgt, mask=mask)
+        d1 = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"], wgt=wgt,
+                        mask=mask)
+        i1 = o1.adjoint(case["uvw"], case["freq"], case["vis"], 128, 128, case["pixsize_x"], case["pixsize_y"],
+                        wgt=wgt, mask=mask)
+        assert rel(res["vis"], d1) < eps and rel(res["img"], i1) < eps
+        assert np.all(res["vis"][mask == 0] == 0)
+        res["plan"].close()
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_and_fully_masked(dev):
+    case = _case_small()
+    empty = dict(case, uvw=np.zeros((0, 3)), vis=np.zeros((0, 1), complex))
+    res = run_product(empty, 1e-5, "f32", torch, dev, dirty=case["dirty"], vis=empty["vis"])
+    assert res["vis"].shape == (0, 1)
+    assert np.all(res["img"] == 0)
+    mask = np.zeros(case["vis"].shape, np.uint8)
+    res = run_product(case, 1e-5, "f32", torch, dev, dirty=case["dirty"], vis=case["vis"], mask=mask)
+    assert res["info"]["n_vis"] == 0
+    assert np.all(res["vis"] == 0) and np.all(res["img"] == 0)
+
+
+def test_single_visibility_and_zero_w(dev):
+    """A lone visibility, and all-zero w (N_w = alpha planes at w-gridding)."""
+    case = _case_small()
+    one = dict(case, uvw=case["uvw"][:1], vis=case["vis"][:1])
+    res = run_product(one, 1e-9, "f64", torch, dev, dirty=case["dirty"], vis=one["vis"])
+    d1 = o1.forward(one["uvw"], one["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"])
+    assert rel(res["vis"], d1) < 1e-9
+    flat = dict(case, uvw=np.concatenate([case["uvw"][:, :2], np.zeros((len(case["uvw"]), 1))], axis=1))
+    res = run_product(flat, 1e-9, "f64", torch, dev, dirty=case["dirty"], vis=case["vis"])
+    assert res["info"]["nw"] == res["info"]["alpha"]
+    d1 = o1.forward(flat["uvw"], flat["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"])
+    assert rel(res["vis"], d1) < 1e-9
+
+
+def test_invalid_arguments(dev):
+    import paper_2010_10122_amd as wg
+    case = _case_small()
+    uvw = torch.from_numpy(case["uvw"]).to(dev)
+    freq = torch.from_numpy(case["freq"]).to(dev)
+    for kw in (dict(npix_x=63), dict(npix_x=30), dict(eps=1e-6, prec="f32"), dict(eps=1e-14, prec="f64"),
+               dict(pix=0.03)):
+        with pytest.raises(wg.WgridError):
+            wg.Plan(uvw, freq, kw.get("npix_x", 64), 64, kw.get("pix", case["pixsize_x"]), case["pixsize_y"],
+                    kw.get("eps", 1e-5), kw.get("prec", "f32"))
+    with pytest.raises(wg.WgridError):
+        wg.Plan(uvw, freq, 64, 64, case["pixsize_x"], case["pixsize_y"], 1e-5, "f32", alpha=12, sigma=1.85)

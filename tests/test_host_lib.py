@@ -1,0 +1,97 @@
+"""CPU checks of the product library: it loads without a GPU, exports every
+symbol include/wgrid.h declares, and its host-side planner agrees with the
+oracle (kernel table, grid sizes, psi, polynomial kernel accuracy, kernel
+choice feasibility).  No device compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import kernel as K
+from oracle import plan as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+wg = pytest.importorskip("paper_2010_10122_amd")
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "wgrid.h")).read()
+    return sorted(set(re.findall(r"\b(wg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2010_10122_amd import _lib
+    lib = _lib.load()
+    names = _header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_strerror():
+    from paper_2010_10122_amd import _lib
+    assert _lib.strerror(0) == "ok"
+    assert "invalid" in _lib.strerror(-1)
+
+
+def test_grid_size_matches_oracle():
+    for sigma in (1.15, 1.35, 1.45, 1.5, 2.0):
+        for n in (32, 64, 100, 512, 1024, 2048, 4096, 8192):
+            assert wg.grid_size(sigma, n) == P.grid_size(sigma, n)
+
+
+def test_kernel_table_matches_oracle_transcription():
+    for a, rows in K.TABLE.items():
+        for s, e, b, m in rows:
+            assert wg.kernel_params(a, s) == (e, b, m)
+    with pytest.raises(Exception):
+        wg.kernel_params(12, 1.85)       # not printed in Appendix A
+
+
+def test_psi_matches_oracle():
+    for a in (4, 7, 8, 12, 16):
+        s = K.TABLE[a][5][0]
+        _, _, b, m = K.table_row(a, s)
+        k = np.linspace(0.0, 0.5 / s, 17)
+        ref = K.psi(k, a, b, m)
+        assert np.max(np.abs(wg.kernel_psi(a, s, k) - ref) / np.abs(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [4, 7, 8, 12, 16])
+def test_polynomial_kernel_accuracy(alpha):
+    """Sect. 4.2: degree <= alpha + 3 piecewise polynomials (Chebyshev-root
+    interpolation) reproduce phi to a fraction of eps_k on every cell.  The
+    edge cells carry (alpha/2 - |t|)^mu, which bounds the achievable error
+    at about 0.3 eps_k for every printed row; below that the FP32/FP64
+    evaluation floor takes over."""
+    for sigma in [row[0] for row in K.TABLE[alpha]]:
+        _, ek, b, m = K.table_row(alpha, sigma)
+        for prec in ("f64", "f32"):
+            coef, deg = wg.kernel_poly(alpha, sigma, prec)
+            assert deg <= alpha + 3
+            z = np.linspace(-1, 1, 301)
+            for i in range(alpha):
+                t = -alpha / 2 + i + (z + 1) / 2
+                p = np.polynomial.polynomial.polyval(z, coef[i])
+                err = np.max(np.abs(p - K.phi(t, alpha, b, m)))
+                bound = max(0.35 * ek, 1e-14 if prec == "f64" else 1e-7)
+                assert err <= bound, (alpha, sigma, prec, i, err)
+
+
+@pytest.mark.parametrize("eps,prec,do_w", [(1e-5, "f32", True), (1e-4, "f32", True), (1e-5, "f32", False),
+                                           (1e-7, "f64", True), (1e-10, "f64", True), (1e-12, "f64", False)])
+def test_kernel_choice_is_feasible(eps, prec, do_w):
+    a, s = wg.select_kernel(eps, prec, do_w, 2048, 2048, 8.5e-5, 8.5e-5, 10 ** 8, 0.0, 2.0e4)
+    assert K.feasible(a, s, eps, do_w)
+    assert s == K.smallest_sigma(a, eps, do_w)
+
+
+def test_kernel_choice_rejects_out_of_range():
+    with pytest.raises(Exception):
+        wg.select_kernel(1e-6, "f32", True, 512, 512, 1e-4, 1e-4, 1000, 0, 100)
+    with pytest.raises(Exception):
+        wg.select_kernel(1e-14, "f64", True, 512, 512, 1e-4, 1e-4, 1000, 0, 100)
