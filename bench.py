@@ -1,0 +1,259 @@
+#!/usr/bin/env python
+"""Benchmark: w-gridding grid & degrid throughput on one MI355X.
+
+Workload (wide field): 2048^2 image over 10 deg, 64 antennas in a 5 km disk,
+8 h at 10 s dumps (5,806,080 rows) x 16 channels over 0.9-1.7 GHz =
+92,897,280 visibilities, 500 point sources; synthetic, seeded.
+
+One step = one forward (degrid) plus one adjoint (grid) application of the
+operator with the plan (kernel choice, corrections, visibility index)
+resident on the device; plan construction is timed separately (cold).
+value = visibilities / mean time of one operator application, FP32 at
+epsilon = 1e-5; the plain FP64 form at the same epsilon is timed beside it.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on
+one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mvis/s grid & degrid at ε=1e-5 FP32 vs plain FP64; p50/p99 serve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(info, kind, n_launch_planes, precision):
+    """Algorithmic HBM bytes of one launch of a kernel kind covering
+    ``n_launch_planes`` w-planes (average batch), from the data each kernel
+    must read and write at least once."""
+    sc = 8.0 if precision == "f32" else 16.0
+    sr = sc / 2
+    nu, nv, nx, ny = info["nu"], info["nv"], info["npix_x"], info["npix_y"]
+    P = n_launch_planes
+    nbatch = math.ceil(info["nw"] / info["planes_per_batch"])
+    f_batch = (info["planes_per_batch"] + info["alpha"] - 1) / info["planes_per_batch"]
+    vis_per_launch = info["n_vis"] * f_batch / nbatch
+    if kind == "grid":           # visibilities + index in, P full grid planes out
+        return P * nu * nv * sc + vis_per_launch * (sc + 4)
+    if kind == "degrid":         # P grid planes in, visibility accumulators updated
+        return P * nu * nv * sc + vis_per_launch * (4 + 2 * sc)
+    if kind == "fft_rows_grid":  # P grid planes in, pruned rows out
+        return P * nu * nv * sc + P * nu * ny * sc
+    if kind == "fft_cols_grid":  # pruned rows in, n-1 in, image accumulator read+write
+        return P * nu * ny * sc + nx * ny * 8 + 2 * nx * ny * sr
+    if kind == "fft_rows_degrid":  # corrected image + n-1 in, P padded rows out
+        return nx * ny * (sr + 8) + P * nx * nv * sc
+    if kind == "fft_cols_degrid":  # P padded rows in, P grid planes out
+        return P * nx * nv * sc + P * nu * nv * sc
+    return float("nan")
+
+
+def cpu_baseline(case, budget_terms=6e8):
+    """Oracle O1 (direct DFT, FP64, OpenMP C) on a bounded sample of the
+    workload: degrid a sample of visibilities against the point-source image
+    (the oracle sums over the non-zero pixels), grid a sample of pixels over
+    a sample of visibilities; both scaled to whole-operator Mvis/s."""
+    import numpy as np
+    from oracle import o1
+    uvw, freq, dirty = case["uvw"], case["freq"], case["dirty"]
+    nrow, nchan = uvw.shape[0], len(freq)
+    n_vis = nrow * nchan
+    rng = np.random.default_rng(99)
+    nsrc = int(np.count_nonzero(dirty))
+    s_deg = int(min(n_vis, budget_terms / 2 / nsrc))
+    idx = rng.choice(n_vis, size=s_deg, replace=False)
+    t0 = time.perf_counter()
+    o1.forward(uvw, freq, dirty, case["pixsize_x"], case["pixsize_y"], vis_idx=idx)
+    t_deg = (time.perf_counter() - t0) / s_deg                        # s per visibility
+    # adjoint: P pixels over the visibilities of a row sample
+    rows = rng.choice(nrow, size=max(1, int(20000 / nchan)), replace=False)
+    vis = case["vis"][rows].astype(np.complex128)
+    npx = int(max(16, budget_terms / 2 / (len(rows) * nchan)))
+    pp = rng.integers(0, case["npix_x"], npx)
+    qq = rng.integers(0, case["npix_y"], npx)
+    t0 = time.perf_counter()
+    o1.adjoint(uvw[rows], freq, vis, case["npix_x"], case["npix_y"], case["pixsize_x"], case["pixsize_y"],
+               pixels=(pp, qq))
+    t_term = (time.perf_counter() - t0) / (npx * len(rows) * nchan)
+    t_grid = t_term * case["npix_x"] * case["npix_y"]                 # s per visibility, full image
+    cores = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    return {
+        "value": 2.0 / (t_deg + t_grid) / 1e6,
+        "unit": "Mvis/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"O1 direct DFT (FP64, OpenMP): degrid of {s_deg} random visibilities against the "
+                   f"{nsrc}-source image; grid of {npx} random pixels over {len(rows) * nchan} visibilities, "
+                   f"scaled to the full {case['npix_x']}^2 image; value = 2/(t_degrid + t_grid) per visibility"),
+        "degrid_mvis_s": 1.0 / t_deg / 1e6,
+        "grid_mvis_s": 1.0 / t_grid / 1e6,
+    }
+
+
+def time_operator(plan, dirty, vis, steps, warmup, prof=None):
+    import torch
+    for _ in range(warmup):
+        plan.degrid(dirty)
+        plan.grid(vis)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_deg = t_grid = 0.0
+    out_v = torch.empty((plan.n_rows, plan.n_chan), dtype=plan.complex_dtype, device=dirty.device)
+    out_i = torch.empty((plan.npix_x, plan.npix_y), dtype=plan.real_dtype, device=dirty.device)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dirty.device)
+    if prof is not None:
+        prof.reset()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(steps):
+        ev[0].record()
+        plan.degrid(dirty, out=out_v, workspace=ws)
+        ev[1].record()
+        plan.grid(vis, out=out_i, workspace=ws)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_deg += ev[0].elapsed_time(ev[1]) / 1e3
+        t_grid += ev[1].elapsed_time(ev[2]) / 1e3
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return t_deg / steps, t_grid / steps, wall, out_v
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--dumps", type=int, default=2880, help="time dumps (2880 = the full 8 h workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2010_10122_amd as wg
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    case = synth.wide_field(n_dumps=args.dumps)
+    n_vis = case["uvw"].shape[0] * len(case["freq"])
+    print(f"[bench] workload {case['name']}: {n_vis} visibilities, generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    uvw = torch.from_numpy(case["uvw"]).to(dev)
+    freq = torch.from_numpy(case["freq"]).to(dev)
+    res = {}
+    prof = wg.Profiler()
+    for prec, eps, steps in (("f32", 1e-5, args.steps), ("f64", 1e-5, args.fp64_steps)):
+        if prec == "f64" and args.no_fp64:
+            continue
+        rdt = torch.float32 if prec == "f32" else torch.float64
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        dirty = torch.from_numpy(case["dirty"]).to(dev, rdt)
+        vis = torch.from_numpy(case["vis"]).to(dev, cdt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = wg.Plan(uvw, freq, case["npix_x"], case["npix_y"], case["pixsize_x"], case["pixsize_y"], eps, prec)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        info = plan.info
+        print(f"[bench] {prec} plan alpha={info['alpha']} sigma={info['sigma']} N={info['nu']} Nw={info['nw']} "
+              f"P={info['planes_per_batch']} in {plan_s:.2f} s", file=sys.stderr, flush=True)
+        with prof:
+            t_deg, t_grid, wall, out_v = time_operator(plan, dirty, vis, steps, args.warmup, prof)
+        kern = prof.read()
+        print(f"[bench] {prec}: degrid {t_deg * 1e3:.1f} ms, grid {t_grid * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        # accuracy spot check of this very output: degrid of 2000 random
+        # visibilities against the direct sum over the 500 sources
+        from oracle import o1
+        idx = np.random.default_rng(7).choice(n_vis, size=2000, replace=False)
+        ref = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"], vis_idx=idx)
+        got = out_v.reshape(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res[prec] = dict(info=info, t_deg=t_deg, t_grid=t_grid, wall=wall, steps=steps, plan_s=plan_s,
+                         kernels=kern, degrid_err=err)
+        plan.close()
+        del dirty, vis
+        torch.cuda.empty_cache()
+
+    r = res["f32"]
+    t_op = 0.5 * (r["t_deg"] + r["t_grid"])
+    value = n_vis / t_op / 1e6
+    # dominant kernel: largest total time in the timed region
+    kern = r["kernels"]
+    dom = max((k for k in kern if kern[k][1] > 0 and k not in ("image", "vis")), key=lambda k: kern[k][0])
+    tot_ms, nl = kern[dom]
+    avg_s = tot_ms / nl / 1e3
+    info = r["info"]
+    planes_per_launch = info["nw"] / math.ceil(info["nw"] / info["planes_per_batch"])
+    bytes_launch = kernel_bytes(info, dom, planes_per_launch, "f32")
+    achieved = bytes_launch / avg_s / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(avg_s * 1e3, 4), "bytes_per_launch": bytes_launch, "launches": nl}
+    per_kernel = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                      "avg_ms": round(v[0] / v[1], 4) if v[1] else None,
+                      "gbs": (round(kernel_bytes(info, k, planes_per_launch, "f32") / (v[0] / v[1] / 1e3) / 1e9, 1)
+                              if v[1] and k not in ("image", "vis") else None)}
+                  for k, v in kern.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mvis/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((r["t_deg"] + r["t_grid"]) * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"wide field: {case['npix_x']}^2 image, 10 deg, {case['uvw'].shape[0]} rows x "
+                         f"{len(case['freq'])} ch = {n_vis} vis, eps=1e-5 FP32"),
+            "npix": case["npix_x"], "n_vis": n_vis, "epsilon": 1e-5,
+            "alpha": info["alpha"], "sigma": info["sigma"], "nu": info["nu"], "nw": info["nw"],
+            "planes_per_batch": info["planes_per_batch"],
+        },
+        "grid_mvis_s": round(n_vis / r["t_grid"] / 1e6, 2),
+        "degrid_mvis_s": round(n_vis / r["t_deg"] / 1e6, 2),
+        "plan_ms": round(r["plan_s"] * 1e3, 1),
+        "degrid_rel_err_vs_oracle": r["degrid_err"],
+        "whole_apply_hbm_frac": round(info["bytes_grid"] / t_op / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": per_kernel,
+        "roofline": roof,
+    }
+    if "f64" in res:
+        f = res["f64"]
+        out["fp64"] = {"grid_mvis_s": round(n_vis / f["t_grid"] / 1e6, 2),
+                       "degrid_mvis_s": round(n_vis / f["t_deg"] / 1e6, 2),
+                       "value": round(n_vis / (0.5 * (f["t_deg"] + f["t_grid"])) / 1e6, 2),
+                       "alpha": f["info"]["alpha"], "sigma": f["info"]["sigma"], "nu": f["info"]["nu"],
+                       "nw": f["info"]["nw"], "degrid_rel_err_vs_oracle": f["degrid_err"],
+                       "plan_ms": round(f["plan_s"] * 1e3, 1)}
+        out["fp32_over_fp64"] = round(value / out["fp64"]["value"], 3)
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(case)
+        print(f"[bench] cpu baseline in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    prof.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

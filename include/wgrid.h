@@ -155,6 +155,33 @@ int wg_plan_index(const wg_plan *plan, void *keys, void *order, void *stream);
 
 const char *wg_strerror(int code);
 
+/* ---- per-kernel timing ----------------------------------------------------
+ * A profiler attached to the calling host thread brackets every kernel
+ * launch of wg_grid / wg_degrid with a pair of HIP events on the launch
+ * stream and accumulates the elapsed time per kernel kind.  Attaching adds
+ * two event records per launch; it changes no result.  A profiler is
+ * owned by the caller and must not be shared between host threads. */
+#define WG_KIND_GRID             0   /* LDS-tile gridder                        */
+#define WG_KIND_DEGRID           1   /* gather degridder                        */
+#define WG_KIND_FFT_ROWS_GRID    2   /* gridding FFT pass 1 (rows)              */
+#define WG_KIND_FFT_COLS_GRID    3   /* gridding FFT pass 2 + screen + accumulate */
+#define WG_KIND_FFT_ROWS_DEGRID  4   /* degridding screen + FFT pass 1 (rows)   */
+#define WG_KIND_FFT_COLS_DEGRID  5   /* degridding FFT pass 2 (columns)         */
+#define WG_KIND_IMAGE            6   /* image-side correction and clearing      */
+#define WG_KIND_VIS              7   /* visibility-side finishing and clearing  */
+#define WG_KIND_COUNT            8
+
+typedef struct wg_profiler wg_profiler;
+int wg_profiler_create(wg_profiler **out);
+int wg_profiler_destroy(wg_profiler *prof);
+/* Attach prof to the calling host thread (NULL detaches). */
+int wg_profiler_attach(wg_profiler *prof);
+/* Totals for one kind since creation or the last reset; waits for the
+ * recorded events to complete. */
+int wg_profiler_read(wg_profiler *prof, int kind, double *total_ms, int64_t *launches);
+int wg_profiler_reset(wg_profiler *prof);
+const char *wg_kernel_kind_name(int kind);
+
 /* ---- host-only helpers (no device needed) -------------------------------
  * These expose pieces of the host planner for inspection and testing. */
 

@@ -7,7 +7,7 @@ Arras et al., "Efficient wide-field radio interferometry response"
     img = plan.grid(vis)            # adjoint R^H, real part (ms2dirty)
 """
 from ._lib import WgridError, WG_F32, WG_F64  # noqa: F401
-from .plan import Plan, grid_size, kernel_params, kernel_poly, kernel_psi, select_kernel  # noqa: F401
+from .plan import Plan, Profiler, grid_size, kernel_params, kernel_poly, kernel_psi, select_kernel  # noqa: F401
 
-__all__ = ["Plan", "WgridError", "WG_F32", "WG_F64", "grid_size", "kernel_params", "kernel_poly",
+__all__ = ["Plan", "Profiler", "WgridError", "WG_F32", "WG_F64", "grid_size", "kernel_params", "kernel_poly",
            "kernel_psi", "select_kernel"]

@@ -73,7 +73,12 @@ EXPORTS = [
     "wg_plan_create", "wg_plan_destroy", "wg_degrid", "wg_grid", "wg_plan_info",
     "wg_workspace_bytes", "wg_plan_bytes", "wg_plan_index", "wg_strerror", "wg_grid_size",
     "wg_kernel_params", "wg_select_kernel", "wg_kernel_poly", "wg_kernel_psi",
+    "wg_profiler_create", "wg_profiler_destroy", "wg_profiler_attach", "wg_profiler_read",
+    "wg_profiler_reset", "wg_kernel_kind_name",
 ]
+
+KIND_NAMES = ["grid", "degrid", "fft_rows_grid", "fft_cols_grid", "fft_rows_degrid", "fft_cols_degrid",
+              "image", "vis"]
 
 _lib = None
 
@@ -124,6 +129,18 @@ def load():
     lib.wg_kernel_poly.restype = ctypes.c_int
     lib.wg_kernel_psi.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, dp]
     lib.wg_kernel_psi.restype = ctypes.c_int
+    lib.wg_profiler_create.argtypes = [ctypes.POINTER(vp)]
+    lib.wg_profiler_create.restype = ctypes.c_int
+    lib.wg_profiler_destroy.argtypes = [vp]
+    lib.wg_profiler_destroy.restype = ctypes.c_int
+    lib.wg_profiler_attach.argtypes = [vp]
+    lib.wg_profiler_attach.restype = ctypes.c_int
+    lib.wg_profiler_read.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.wg_profiler_read.restype = ctypes.c_int
+    lib.wg_profiler_reset.argtypes = [vp]
+    lib.wg_profiler_reset.restype = ctypes.c_int
+    lib.wg_kernel_kind_name.argtypes = [ctypes.c_int]
+    lib.wg_kernel_kind_name.restype = ctypes.c_char_p
     _lib = lib
     return lib
 

@@ -286,6 +286,53 @@ double predict_seconds(int alpha, double sigma, int precision, int do_w, int npi
     return t_planes + t_vis;
 }
 
+// Root-mean-square over the image of Psi(0)/Psi(l, m): the factor by which
+// the correction 1/(n Psi) magnifies the rounding noise of the gridded planes
+// and of the FFTs (largest towards the image corners, where all three kernel
+// transforms approach the edge of the retained band).  Sampled at the
+// centres of a 32 x 32 partition of the image.
+double rounding_amplification(int alpha, double sigma, int do_w, int npix_x, int npix_y, double px,
+                              double py) {
+    const KernelRow *r = find_row(alpha, sigma);
+    if (!r) return std::numeric_limits<double>::infinity();
+    std::vector<double> t, w;
+    psi_nodes(alpha, r->beta, r->mu, t, w);
+    const double p0 = psi_eval(0.0, t, w);
+    const int nu = grid_size(sigma, npix_x), nv = grid_size(sigma, npix_y);
+    const double dw = do_w ? 1.0 / (2.0 * sigma * max_abs_nm1(npix_x, npix_y, px, py)) : 0.0;
+    const int S = 32;
+    std::vector<double> ix(S), iy(S), psx(S), psy(S);
+    for (int i = 0; i < S; ++i) {
+        ix[i] = std::floor((i + 0.5) * npix_x / S) - npix_x / 2;
+        iy[i] = std::floor((i + 0.5) * npix_y / S) - npix_y / 2;
+        psx[i] = psi_eval(ix[i] / nu, t, w) / p0;
+        psy[i] = psi_eval(iy[i] / nv, t, w) / p0;
+    }
+    double acc = 0.0;
+    for (int i = 0; i < S; ++i) {
+        for (int j = 0; j < S; ++j) {
+            double ps = psx[i] * psy[j];
+            if (do_w) {
+                double l = ix[i] * px, m = iy[j] * py;
+                double rho = l * l + m * m;
+                double nm1 = -rho / (1.0 + std::sqrt(1.0 - rho));
+                ps *= psi_eval(nm1 * dw, t, w) / p0;
+            }
+            acc += 1.0 / (ps * ps);
+        }
+    }
+    return std::sqrt(acc / (S * S));
+}
+
+// Rounding error of one apply relative to the result's norm: measured on
+// MI355X at 0.2-1.1 unit roundoffs times the amplification above, over all
+// printed supports in both precisions; 1.2 is taken as the bound.
+double rounding_error(int alpha, double sigma, int precision, int do_w, int npix_x, int npix_y, double px,
+                      double py) {
+    const double ulp = precision == 0 ? 5.96e-8 : 1.11e-16;
+    return 1.2 * ulp * rounding_amplification(alpha, sigma, do_w, npix_x, npix_y, px, py);
+}
+
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,
                   double py, int64_t n_vis, double wmin, double wmax, int *alpha,
                   double *sigma, double *seconds) {
@@ -296,7 +343,16 @@ int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, d
     double bs = 0.0;
     const int npmax = npix_x > npix_y ? npix_x : npix_y;
     for (int a : kSupports) {
-        const KernelRow *r = smallest_feasible(a, eps, factor);
+        // smallest printed sigma whose kernel error plus the estimated
+        // rounding error of this precision stays within eps
+        const KernelRow *r = nullptr;
+        const KernelRow *end = kTable + sizeof(kTable) / sizeof(kTable[0]);
+        for (const KernelRow *c = smallest_feasible(a, eps, factor); c && c < end && c->alpha == a; ++c) {
+            if (factor * c->eps + rounding_error(a, c->sigma, precision, do_w, npix_x, npix_y, px, py) <= eps) {
+                r = c;
+                break;
+            }
+        }
         if (!r) continue;
         if (grid_size(r->sigma, npmax) > max_grid(precision)) continue;
         double t = predict_seconds(a, r->sigma, precision, do_w, npix_x, npix_y, mn, n_vis, wmin, wmax);

@@ -33,6 +33,10 @@ int choose_degree(int alpha, double beta, double mu, double eps_k, int precision
 double max_abs_nm1(int npix_x, int npix_y, double pixsize_x, double pixsize_y);
 double predict_seconds(int alpha, double sigma, int precision, int do_w, int npix_x, int npix_y,
                        double max_nm1, int64_t n_vis, double wmin, double wmax);
+double rounding_amplification(int alpha, double sigma, int do_w, int npix_x, int npix_y, double px,
+                              double py);
+double rounding_error(int alpha, double sigma, int precision, int do_w, int npix_x, int npix_y, double px,
+                      double py);
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,
                   double py, int64_t n_vis, double wmin, double wmax, int *alpha, double *sigma,
                   double *seconds);

@@ -40,6 +40,75 @@ bool hip_ok(hipError_t e, const char *what) {
     } while (0)
 
 // Device allocations of one plan, through the caller's allocator if given.
+// Optional per-kernel timing: while a profiler is attached to the calling
+// host thread, every launch of the apply pipeline is bracketed by a pair of
+// HIP events on the launch stream.  Events come from a pool and are read
+// (synchronising on them) only by wg_profiler_read.
+}  // namespace
+
+struct wg_profiler {
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[WG_KIND_COUNT] = {};
+    int64_t launches[WG_KIND_COUNT] = {};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+    void drain() {
+        for (Rec &r : pending) {
+            float ms = 0.f;
+            if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                total_ms[r.kind] += ms;
+                launches[r.kind] += 1;
+            } else {
+                (void)hipGetLastError();
+            }
+            if (r.a) pool.push_back(r.a);
+            if (r.b) pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+};
+
+namespace {
+
+thread_local wg_profiler *g_prof = nullptr;
+
+// Scope guard recording one launch of `kind` on `st` when profiling.
+struct ProfScope {
+    wg_profiler *p;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    ProfScope(int k, hipStream_t s) : p(g_prof), kind(k), st(s) {
+        if (p) {
+            a = p->get();
+            b = p->get();
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (p) {
+            if (b) (void)hipEventRecord(b, st);
+            p->pending.push_back({kind, a, b});
+        }
+    }
+};
+
 struct DevMem {
     wg_alloc_fn alloc = nullptr;
     wg_free_fn free = nullptr;
@@ -565,37 +634,73 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     PassGeom pg{g.nu, g.nv, g.npix_x, g.npix_y, p->P, g.nw, g.do_w, g.w0, g.dw};
 
     if (gridding) {
-        hipLaunchKernelGGL(k_fill_zero<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st, acc, npix);
+        {
+            ProfScope ps(WG_KIND_IMAGE, st);
+            hipLaunchKernelGGL(k_fill_zero<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st, acc,
+                               npix);
+        }
         if (p->n_active > 0) {
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
-                launch_vis_kernel<R>(true, p, va, J, G, nullptr, st);
-                DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_grid(p, G, T, pg, np, st)));
-                DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                {
+                    ProfScope ps(WG_KIND_GRID, st);
+                    launch_vis_kernel<R>(true, p, va, J, G, nullptr, st);
+                }
+                {
+                    ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_grid(p, G, T, pg, np, st)));
+                }
+                {
+                    ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
+                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                }
             }
         }
-        hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st, acc,
-                           p->corr, (R *)out, npix);
+        {
+            ProfScope ps(WG_KIND_IMAGE, st);
+            hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st,
+                               acc, p->corr, (R *)out, npix);
+        }
     } else {
-        if (p->n_total > 0 && d.mask)
+        if (p->n_total > 0 && d.mask) {
+            ProfScope ps(WG_KIND_VIS, st);
             hipLaunchKernelGGL(k_zero_masked<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256), 0,
                                st, d.mask, p->n_total, (C *)out);
+        }
         if (p->n_active > 0) {
-            hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st,
-                               (const R *)in, p->corr, itil, npix);
-            hipLaunchKernelGGL(k_fill_zero<C>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256), 0,
-                               st, vacc, p->n_active);
+            {
+                ProfScope ps(WG_KIND_IMAGE, st);
+                hipLaunchKernelGGL(k_scale_image<R>, dim3((unsigned)grid_blocks(npix, 256, 1 << 16)), dim3(256), 0, st,
+                                   (const R *)in, p->corr, itil, npix);
+            }
+            {
+                ProfScope ps(WG_KIND_VIS, st);
+                hipLaunchKernelGGL(k_fill_zero<C>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
+                                   0, st, vacc, p->n_active);
+            }
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
-                DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_degrid(p, itil, T, pg, j_lo, np, st)));
-                DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_degrid(p, T, G, pg, np, st)));
-                launch_vis_kernel<R>(false, p, va, J, G, vacc, st);
+                {
+                    ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_degrid(p, itil, T, pg, j_lo, np, st)));
+                }
+                {
+                    ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
+                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_degrid(p, T, G, pg, np, st)));
+                }
+                {
+                    ProfScope ps(WG_KIND_DEGRID, st);
+                    launch_vis_kernel<R>(false, p, va, J, G, vacc, st);
+                }
             }
-            hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256), 0,
-                               st, vacc, p->order, d.uvw, p->scale, (const R *)wgt, p->n_active, d.n_chan, g.do_w,
-                               (C *)out);
+            {
+                ProfScope ps(WG_KIND_VIS, st);
+                hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
+                                   0, st, vacc, p->order, d.uvw, p->scale, (const R *)wgt, p->n_active, d.n_chan,
+                                   g.do_w, (C *)out);
+            }
         }
     }
     if (!hip_ok(hipGetLastError(), gridding ? "wg_grid launch" : "wg_degrid launch")) return WG_EHIP;
@@ -717,6 +822,50 @@ int wg_plan_index(const wg_plan *p, void *keys, void *order, void *stream) {
     if (order)
         HIP_TRY(hipMemcpyAsync(order, p->order, p->n_active * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     return WG_OK;
+}
+
+int wg_profiler_create(wg_profiler **out) {
+    if (!out) return WG_EINVAL;
+    *out = new (std::nothrow) wg_profiler();
+    return *out ? WG_OK : WG_ENOMEM;
+}
+
+int wg_profiler_destroy(wg_profiler *p) {
+    if (!p) return WG_OK;
+    if (g_prof == p) g_prof = nullptr;
+    p->drain();
+    for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+    delete p;
+    return WG_OK;
+}
+
+int wg_profiler_attach(wg_profiler *p) {
+    g_prof = p;
+    return WG_OK;
+}
+
+int wg_profiler_read(wg_profiler *p, int kind, double *total_ms, int64_t *launches) {
+    if (!p || kind < 0 || kind >= WG_KIND_COUNT) return WG_EINVAL;
+    p->drain();
+    if (total_ms) *total_ms = p->total_ms[kind];
+    if (launches) *launches = p->launches[kind];
+    return WG_OK;
+}
+
+int wg_profiler_reset(wg_profiler *p) {
+    if (!p) return WG_EINVAL;
+    p->drain();
+    for (int k = 0; k < WG_KIND_COUNT; ++k) {
+        p->total_ms[k] = 0.0;
+        p->launches[k] = 0;
+    }
+    return WG_OK;
+}
+
+const char *wg_kernel_kind_name(int kind) {
+    static const char *names[WG_KIND_COUNT] = {"grid", "degrid", "fft_rows_grid", "fft_cols_grid",
+                                               "fft_rows_degrid", "fft_cols_degrid", "image", "vis"};
+    return kind >= 0 && kind < WG_KIND_COUNT ? names[kind] : "unknown";
 }
 
 const char *wg_strerror(int code) {

@@ -163,6 +163,49 @@ class Plan:
         return keys, order
 
 
+class Profiler:
+    """Per-kernel HIP-event timing of wg_grid / wg_degrid launches made by the
+    calling thread while attached (``with Profiler() as prof: ...``)."""
+
+    def __init__(self):
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(self._lib.wg_profiler_create(ctypes.byref(h)), "wg_profiler_create")
+        self._h = h
+
+    def __enter__(self):
+        self._lib.wg_profiler_attach(self._h)
+        return self
+
+    def __exit__(self, *exc):
+        self._lib.wg_profiler_attach(None)
+        return False
+
+    def reset(self):
+        _lib.check(self._lib.wg_profiler_reset(self._h), "wg_profiler_reset")
+
+    def read(self):
+        """{kind: (total_ms, launches)} for every kernel kind."""
+        out = {}
+        for k, name in enumerate(_lib.KIND_NAMES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _lib.check(self._lib.wg_profiler_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)),
+                       "wg_profiler_read")
+            out[name] = (ms.value, n.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wg_profiler_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---- host-only helpers --------------------------------------------------------
 
 def grid_size(sigma, npix):

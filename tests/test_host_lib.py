@@ -87,7 +87,9 @@ def test_polynomial_kernel_accuracy(alpha):
 def test_kernel_choice_is_feasible(eps, prec, do_w):
     a, s = wg.select_kernel(eps, prec, do_w, 2048, 2048, 8.5e-5, 8.5e-5, 10 ** 8, 0.0, 2.0e4)
     assert K.feasible(a, s, eps, do_w)
-    assert s == K.smallest_sigma(a, eps, do_w)
+    # the rounding-aware choice may take a larger sigma than the smallest
+    # printed one that meets eps on kernel error alone, never a smaller one
+    assert s >= K.smallest_sigma(a, eps, do_w)
 
 
 def test_kernel_choice_rejects_out_of_range():
