@@ -33,26 +33,58 @@ template <typename R> struct VisArgs {
 // tile itself and in the three neighbouring tiles up/left (a footprint spans
 // at most alpha <= 16 cells).  No two workgroups write the same grid cell,
 // so the tile is flushed with plain coalesced stores, zeros included.
+//
+// Visibilities are taken in chunks.  Phase 1, one thread per visibility:
+// coordinates, weighted value and the 3 x alpha kernel values go to LDS.
+// Phase 2, one wave per visibility (or per alpha^2-lane group of it): lane
+// = footprint cell, so the LDS atomic adds of one instruction never collide;
+// the padded tile row stride keeps an 8 x 8 footprint free of bank
+// conflicts.  Waves working on different visibilities meet only through the
+// atomics.
 // ---------------------------------------------------------------------------
+constexpr int kAccStride = 20;                      // LDS row stride of an accumulator tile
+constexpr int kAccPlane = kTileCells * kAccStride;  // floats per plane and component
+
+template <typename R, int ALPHA> struct GridStage {
+    static constexpr int CH = (sizeof(R) == 8 || ALPHA >= 12) ? 128 : 256;   // visibilities per chunk
+    static constexpr int INTS = 4;                 // la0, lb0, p0 | p1 << 16, kofs
+    static constexpr int REALS = 2 + 3 * ALPHA;    // d.re, d.im, ku, kv, kw
+    static constexpr size_t bytes = (size_t)CH * (INTS * 4 + REALS * sizeof(R));
+};
+
 template <typename R, int ALPHA>
 __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__restrict__ G) {
     using C = Cx<R>;
+    using ST = GridStage<R, ALPHA>;
+    constexpr int CH = ST::CH;
+    constexpr int CELLS = ALPHA * ALPHA;
+    constexpr int VPW = CELLS <= 64 ? 64 / CELLS : 1;        // visibilities per wave step
+    constexpr int PASSES = (CELLS + 63) / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *acc_re = reinterpret_cast<R *>(smem_raw);
-    R *acc_im = acc_re + a.P * kTileArea;
+    R *acc_im = acc_re + a.P * kAccPlane;
+    R *s_real = acc_im + a.P * kAccPlane;                     // [REALS][CH]
+    int *s_int = reinterpret_cast<int *>(s_real + ST::REALS * CH);   // [INTS][CH]
+    R *s_dre = s_real, *s_dim = s_real + CH;
+    R *s_ku = s_real + 2 * CH, *s_kv = s_ku + ALPHA * CH, *s_kw = s_kv + ALPHA * CH;   // [ALPHA][CH]
+    int *s_la = s_int, *s_lb = s_int + CH, *s_pr = s_int + 2 * CH, *s_ko = s_int + 3 * CH;
+
     const Geom &g = a.g;
     const int ntiles = g.ntu * g.ntv;
     const int tile = xcd_remap(blockIdx.x, ntiles);
     if (tile < 0) return;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < a.P * kTileArea; e += blockDim.x) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < a.P * kAccPlane; e += blockDim.x) {
         acc_re[e] = (R)0;
         acc_im[e] = (R)0;
     }
-    __syncthreads();
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
+    // the four contributing bins as one concatenated list
+    uint32_t b_s0[4], b_end[4];
+    uint32_t total = 0;
+#pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         int tu = A - 1 + (nb >> 1);
         int tv = B - 1 + (nb & 1);
@@ -61,58 +93,95 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
         const int64_t bin = (int64_t)tu * g.ntv + tv;
         const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
         const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
-        for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
-            const uint32_t idx = a.order[s];
-            const int64_t r = idx / g.n_chan;
-            const int64_t c = idx - r * g.n_chan;
-            const VisCoord vc = vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
-            int la0 = vc.iu - A * kTileCells;
-            int lb0 = vc.iv - B * kTileCells;
-            if (la0 > g.nu / 2) la0 -= g.nu;
-            if (lb0 > g.nv / 2) lb0 -= g.nv;
-            C d = a.vis[idx];
-            if (a.wgt) d = cscale(d, a.wgt[idx]);
-            if (vc.flip) d.y = -d.y;
-            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
-            kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
-            if (g.do_w) {
-                kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
-            } else {
+        const uint32_t n = s1 > s0 ? s1 - s0 : 0u;
+        b_s0[nb] = s0;
+        total += n;
+        b_end[nb] = total;
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < total; base += CH) {
+        // ---- phase 1: one thread per visibility -------------------------
+        if (tid < CH) {
+            const uint32_t pos = base + tid;
+            int pr = 0;                                   // empty plane range
+            if (pos < total) {
+                int nb = pos < b_end[0] ? 0 : pos < b_end[1] ? 1 : pos < b_end[2] ? 2 : 3;
+                const uint32_t s = b_s0[nb] + (pos - (nb ? b_end[nb - 1] : 0u));
+                const uint32_t idx = a.order[s];
+                const int64_t r = idx / g.n_chan;
+                const int64_t c = idx - r * g.n_chan;
+                const VisCoord vc =
+                    vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
+                int la0 = vc.iu - A * kTileCells;
+                int lb0 = vc.iv - B * kTileCells;
+                if (la0 > g.nu / 2) la0 -= g.nu;
+                if (lb0 > g.nv / 2) lb0 -= g.nv;
+                C d = a.vis[idx];
+                if (a.wgt) d = cscale(d, a.wgt[idx]);
+                if (vc.flip) d.y = -d.y;
+                R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+                kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
+                kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+                int p0, p1;
+                if (g.do_w) {
+                    kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+                    p0 = max(vc.iw, j_lo) - j_lo;
+                    p1 = min(vc.iw + ALPHA, j_hi) - j_lo;
+                } else {
 #pragma unroll
-                for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
-            }
-            const int nplanes_vis = g.do_w ? ALPHA : 1;
-#pragma unroll
-            for (int jw = 0; jw < ALPHA; ++jw) {
-                const int j = vc.iw + jw;
-                if (jw >= nplanes_vis || j < j_lo || j >= j_hi) continue;
-                const C dj = cscale(d, kw[jw]);
-                R *pre = acc_re + (j - j_lo) * kTileArea;
-                R *pim = acc_im + (j - j_lo) * kTileArea;
+                    for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
+                    p0 = 0;
+                    p1 = 1;
+                }
+                if (p1 < p0) p1 = p0;
+                pr = p0 | (p1 << 16);
+                s_la[tid] = la0;
+                s_lb[tid] = lb0;
+                s_ko[tid] = j_lo - vc.iw;                  // kw index = p + kofs
+                s_dre[tid] = d.x;
+                s_dim[tid] = d.y;
 #pragma unroll
                 for (int i = 0; i < ALPHA; ++i) {
-                    const int la = la0 + i;
-                    if (la < 0 || la >= kTileCells) continue;
-                    const R fr = dj.x * ku[i], fi = dj.y * ku[i];
+                    s_ku[i * CH + tid] = ku[i];
+                    s_kv[i * CH + tid] = kv[i];
+                    s_kw[i * CH + tid] = kw[i];
+                }
+            }
+            s_pr[tid] = pr;
+        }
+        __syncthreads();
+        // ---- phase 2: lanes = footprint cells --------------------------
+        const int cnt = (int)min<uint32_t>((uint32_t)CH, total - base);
+        for (int v0 = wave * VPW; v0 < cnt; v0 += 4 * VPW) {
 #pragma unroll
-                    for (int k = 0; k < ALPHA; ++k) {
-                        const int lb = lb0 + k;
-                        if (lb < 0 || lb >= kTileCells) continue;
-                        atomicAdd(&pre[la * kTileCells + lb], fr * kv[k]);
-                        atomicAdd(&pim[la * kTileCells + lb], fi * kv[k]);
-                    }
+            for (int pass = 0; pass < PASSES; ++pass) {
+                const int cl = CELLS <= 64 ? lane % CELLS : pass * 64 + lane;
+                const int v = CELLS <= 64 ? v0 + lane / CELLS : v0;
+                const bool lane_ok = (CELLS <= 64 ? lane < VPW * CELLS : cl < CELLS) && v < cnt;
+                if (!lane_ok) continue;
+                const int i = cl / ALPHA, k = cl - (cl / ALPHA) * ALPHA;
+                const int la = s_la[v] + i, lb = s_lb[v] + k;
+                if (la < 0 || la >= kTileCells || lb < 0 || lb >= kTileCells) continue;
+                const R wuv = s_ku[i * CH + v] * s_kv[k * CH + v];
+                const R fr = s_dre[v] * wuv, fi = s_dim[v] * wuv;
+                const int pr = s_pr[v], ko = s_ko[v];
+                const int cell = la * kAccStride + lb;
+                for (int p = pr & 0xffff; p < (pr >> 16); ++p) {
+                    const R kwv = s_kw[(p + ko) * CH + v];
+                    atomicAdd(&acc_re[p * kAccPlane + cell], fr * kwv);
+                    atomicAdd(&acc_im[p * kAccPlane + cell], fi * kwv);
                 }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     const int np = j_hi - j_lo;
     for (int e = tid; e < np * kTileArea; e += blockDim.x) {
         const int p = e / kTileArea, cell = e - p * kTileArea;
         const int la = cell / kTileCells, lb = cell - la * kTileCells;
         const int64_t off = ((int64_t)p * g.nu + (A * kTileCells + la)) * g.nv + (B * kTileCells + lb);
-        G[off] = cmake<C>(acc_re[e], acc_im[e]);
+        const int src = p * kAccPlane + la * kAccStride + lb;
+        G[off] = cmake<C>(acc_re[src], acc_im[src]);
     }
 }
 

@@ -206,8 +206,8 @@ def test_invalid_arguments(dev):
     freq = torch.from_numpy(case["freq"]).to(dev)
     for kw in (dict(npix_x=63), dict(npix_x=30), dict(eps=1e-6, prec="f32"), dict(eps=1e-14, prec="f64"),
                dict(pix=0.03)):
+        pix = kw.get("pix", case["pixsize_x"])
         with pytest.raises(wg.WgridError):
-            wg.Plan(uvw, freq, kw.get("npix_x", 64), 64, kw.get("pix", case["pixsize_x"]), case["pixsize_y"],
-                    kw.get("eps", 1e-5), kw.get("prec", "f32"))
+            wg.Plan(uvw, freq, kw.get("npix_x", 64), 64, pix, pix, kw.get("eps", 1e-5), kw.get("prec", "f32"))
     with pytest.raises(wg.WgridError):
         wg.Plan(uvw, freq, 64, 64, case["pixsize_x"], case["pixsize_y"], 1e-5, "f32", alpha=12, sigma=1.85)

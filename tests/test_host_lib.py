@@ -97,3 +97,35 @@ def test_kernel_choice_rejects_out_of_range():
         wg.select_kernel(1e-6, "f32", True, 512, 512, 1e-4, 1e-4, 1000, 0, 100)
     with pytest.raises(Exception):
         wg.select_kernel(1e-14, "f64", True, 512, 512, 1e-4, 1e-4, 1000, 0, 100)
+
+
+def test_plan_create_rejects_invalid_arguments_before_device_work():
+    """Argument validation of wg_plan_create happens on the host before any
+    HIP call, so it is checkable without a GPU (the pointers below are never
+    dereferenced)."""
+    from paper_2010_10122_amd import _lib
+    lib = _lib.load()
+    pix = 1.45e-4
+
+    def desc(**kw):
+        d = _lib.PlanDesc()
+        d.uvw, d.freq, d.mask = 4096, 8192, None
+        d.n_rows, d.n_chan = 100, 2
+        d.npix_x = d.npix_y = 64
+        d.pixsize_x = d.pixsize_y = pix
+        d.epsilon, d.precision, d.do_wgridding = 1e-5, _lib.WG_F32, 1
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+
+    bad = [dict(npix_x=63), dict(npix_y=30), dict(pixsize_x=0.0), dict(epsilon=1e-6),
+           dict(epsilon=1e-14, precision=_lib.WG_F64), dict(epsilon=0.5), dict(precision=7),
+           dict(n_chan=0), dict(n_rows=-1), dict(uvw=None), dict(freq=None),
+           dict(n_rows=2 ** 31, n_chan=2), dict(alpha=12, sigma=1.85), dict(alpha=9, sigma=1.5),
+           dict(pixsize_x=0.03, pixsize_y=0.03), dict(planes_per_batch=-2)]
+    for kw in bad:
+        h = ctypes.c_void_p()
+        d = desc(**kw)
+        assert lib.wg_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.WG_EINVAL, kw
+        assert not h.value
+    assert lib.wg_plan_create(None, None) == _lib.WG_EINVAL
