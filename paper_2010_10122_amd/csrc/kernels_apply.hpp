@@ -36,17 +36,19 @@ template <typename R> struct VisArgs {
 //
 // Visibilities are taken in chunks.  Phase 1, one thread per visibility:
 // coordinates, weighted value and the 3 x alpha kernel values go to LDS.
-// Phase 2, one wave per visibility (or per alpha^2-lane group of it): lane
-// = footprint cell, so the LDS atomic adds of one instruction never collide;
-// the padded tile row stride keeps an 8 x 8 footprint free of bank
-// conflicts.  Waves working on different visibilities meet only through the
-// atomics.
+// Phase 2: wave w owns the planes p = w (mod 4) of the tile and walks every
+// staged visibility with lane = footprint cell.  Lanes of one instruction
+// touch distinct cells and no other wave touches those planes, so the
+// accumulation is a plain LDS read-modify-write, without atomics.  The
+// padded row stride keeps two footprint rows of a quarter-wave on disjoint
+// banks.
 // ---------------------------------------------------------------------------
-constexpr int kAccStride = 20;                      // LDS row stride of an accumulator tile
-constexpr int kAccPlane = kTileCells * kAccStride;  // floats per plane and component
+constexpr int kAccStride = 24;                      // LDS row stride (complex) of an accumulator tile
+constexpr int kAccPlane = kTileCells * kAccStride;  // complex values per plane
+constexpr int kGridWaves = 4;                       // waves per gridder workgroup
 
 template <typename R, int ALPHA> struct GridStage {
-    static constexpr int CH = (sizeof(R) == 8 || ALPHA >= 12) ? 128 : 256;   // visibilities per chunk
+    static constexpr int CH = 128;                 // visibilities per chunk
     static constexpr int INTS = 4;                 // la0, lb0, p0 | p1 << 16, kofs
     static constexpr int REALS = 2 + 3 * ALPHA;    // d.re, d.im, ku, kv, kw
     static constexpr size_t bytes = (size_t)CH * (INTS * 4 + REALS * sizeof(R));
@@ -61,9 +63,8 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
     constexpr int VPW = CELLS <= 64 ? 64 / CELLS : 1;        // visibilities per wave step
     constexpr int PASSES = (CELLS + 63) / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *acc_re = reinterpret_cast<R *>(smem_raw);
-    R *acc_im = acc_re + a.P * kAccPlane;
-    R *s_real = acc_im + a.P * kAccPlane;                     // [REALS][CH]
+    C *acc = reinterpret_cast<C *>(smem_raw);                 // [P][16][kAccStride]
+    R *s_real = reinterpret_cast<R *>(acc + a.P * kAccPlane);  // [REALS][CH]
     int *s_int = reinterpret_cast<int *>(s_real + ST::REALS * CH);   // [INTS][CH]
     R *s_dre = s_real, *s_dim = s_real + CH;
     R *s_ku = s_real + 2 * CH, *s_kv = s_ku + ALPHA * CH, *s_kw = s_kv + ALPHA * CH;   // [ALPHA][CH]
@@ -75,10 +76,7 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
     if (tile < 0) return;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < a.P * kAccPlane; e += blockDim.x) {
-        acc_re[e] = (R)0;
-        acc_im[e] = (R)0;
-    }
+    for (int e = tid; e < a.P * kAccPlane; e += blockDim.x) acc[e] = cmake<C>((R)0, (R)0);
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
     // the four contributing bins as one concatenated list
@@ -150,26 +148,32 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
             s_pr[tid] = pr;
         }
         __syncthreads();
-        // ---- phase 2: lanes = footprint cells --------------------------
+        // ---- phase 2: wave owns planes p = wave (mod 4); lanes = cells ----
         const int cnt = (int)min<uint32_t>((uint32_t)CH, total - base);
-        for (int v0 = wave * VPW; v0 < cnt; v0 += 4 * VPW) {
+        for (int v0 = 0; v0 < cnt; v0 += VPW) {
 #pragma unroll
             for (int pass = 0; pass < PASSES; ++pass) {
                 const int cl = CELLS <= 64 ? lane % CELLS : pass * 64 + lane;
                 const int v = CELLS <= 64 ? v0 + lane / CELLS : v0;
                 const bool lane_ok = (CELLS <= 64 ? lane < VPW * CELLS : cl < CELLS) && v < cnt;
                 if (!lane_ok) continue;
+                const int pr = s_pr[v];
+                const int p0 = pr & 0xffff, p1 = pr >> 16;
+                int p = p0 + ((wave - p0) & (kGridWaves - 1));   // first plane of this wave
+                if (p >= p1) continue;
                 const int i = cl / ALPHA, k = cl - (cl / ALPHA) * ALPHA;
                 const int la = s_la[v] + i, lb = s_lb[v] + k;
                 if (la < 0 || la >= kTileCells || lb < 0 || lb >= kTileCells) continue;
                 const R wuv = s_ku[i * CH + v] * s_kv[k * CH + v];
                 const R fr = s_dre[v] * wuv, fi = s_dim[v] * wuv;
-                const int pr = s_pr[v], ko = s_ko[v];
-                const int cell = la * kAccStride + lb;
-                for (int p = pr & 0xffff; p < (pr >> 16); ++p) {
+                const int ko = s_ko[v];
+                C *cellp = acc + la * kAccStride + lb;
+                for (; p < p1; p += kGridWaves) {
                     const R kwv = s_kw[(p + ko) * CH + v];
-                    atomicAdd(&acc_re[p * kAccPlane + cell], fr * kwv);
-                    atomicAdd(&acc_im[p * kAccPlane + cell], fi * kwv);
+                    C cur = cellp[p * kAccPlane];
+                    cur.x += fr * kwv;
+                    cur.y += fi * kwv;
+                    cellp[p * kAccPlane] = cur;
                 }
             }
         }
@@ -180,8 +184,7 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
         const int p = e / kTileArea, cell = e - p * kTileArea;
         const int la = cell / kTileCells, lb = cell - la * kTileCells;
         const int64_t off = ((int64_t)p * g.nu + (A * kTileCells + la)) * g.nv + (B * kTileCells + lb);
-        const int src = p * kAccPlane + la * kAccStride + lb;
-        G[off] = cmake<C>(acc_re[src], acc_im[src]);
+        G[off] = acc[p * kAccPlane + la * kAccStride + lb];
     }
 }
 

@@ -525,7 +525,7 @@ template <typename R, int ALPHA> struct Launch {
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, hipStream_t st) {
         const int nt = p->g.ntu * p->g.ntv;
         const int nb = ((nt + 7) / 8) * 8;
-        const size_t lds = 2 * (size_t)p->P * kAccPlane * sizeof(R) + GridStage<R, ALPHA>::bytes;
+        const size_t lds = (size_t)p->P * kAccPlane * sizeof(Cx<R>) + GridStage<R, ALPHA>::bytes;
         hipLaunchKernelGGL((k_grid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G);
     }
     static void degrid(const wg_plan *p, const VisArgs<R> &va, int J, const Cx<R> *G, Cx<R> *vacc,
