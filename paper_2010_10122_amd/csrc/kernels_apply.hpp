@@ -28,30 +28,25 @@ template <typename R> struct VisArgs {
 
 // ---------------------------------------------------------------------------
 // Gridder (adjoint, eq. Rad2 before the FFT).  One workgroup owns one 16x16
-// tile of the grid for the P planes of batch J and accumulates in LDS every
+// tile of the grid for the P = alpha planes of batch J and accumulates every
 // visibility whose kernel footprint reaches the tile: those anchored in the
 // tile itself and in the three neighbouring tiles up/left (a footprint spans
 // at most alpha <= 16 cells).  No two workgroups write the same grid cell,
-// so the tile is flushed with plain coalesced stores, zeros included.
+// so the tile is flushed with plain stores, zeros included.
 //
 // Visibilities are taken in chunks.  Phase 1, one thread per visibility:
-// coordinates, weighted value and the 3 x alpha kernel values go to LDS.
-// Phase 2: wave w owns the planes p = w (mod 4) of the tile and walks every
-// staged visibility with lane = footprint cell.  Lanes of one instruction
-// touch distinct cells and no other wave touches those planes, so the
-// accumulation is a plain LDS read-modify-write, without atomics.  The
-// padded row stride keeps two footprint rows of a quarter-wave on disjoint
-// banks.
+// tile-relative anchor, weighted value, the u and v kernel values and the w
+// weights rotated onto the batch's plane slots go to LDS.  Phase 2: wave w
+// owns quadrant w (8 x 8 cells) of the tile, lane = cell, and holds that
+// cell's P plane accumulators in registers; for every staged visibility
+// whose footprint meets the quadrant it adds value * ku * kv * kw[slot] to
+// each slot.  Every LDS access in phase 2 is a read, so waves never wait on
+// each other and need no atomics.
 // ---------------------------------------------------------------------------
-constexpr int kAccStride = 24;                      // LDS row stride (complex) of an accumulator tile
-constexpr int kAccPlane = kTileCells * kAccStride;  // complex values per plane
-constexpr int kGridWaves = 4;                       // waves per gridder workgroup
-
 template <typename R, int ALPHA> struct GridStage {
-    static constexpr int CH = 128;                 // visibilities per chunk
-    static constexpr int INTS = 4;                 // la0, lb0, p0 | p1 << 16, kofs
-    static constexpr int REALS = 2 + 3 * ALPHA;    // d.re, d.im, ku, kv, kw
-    static constexpr size_t bytes = (size_t)CH * (INTS * 4 + REALS * sizeof(R));
+    static constexpr int CH = (sizeof(R) == 8 && ALPHA >= 12) ? 128 : 256;   // visibilities per chunk
+    static constexpr int REALS = 2 + 3 * ALPHA;    // d.re, d.im, ku[alpha], kv[alpha], kw slots[alpha]
+    static constexpr size_t bytes = (size_t)CH * (2 * sizeof(int) + REALS * sizeof(R));
 };
 
 template <typename R, int ALPHA>
@@ -59,16 +54,13 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
     using C = Cx<R>;
     using ST = GridStage<R, ALPHA>;
     constexpr int CH = ST::CH;
-    constexpr int CELLS = ALPHA * ALPHA;
-    constexpr int VPW = CELLS <= 64 ? 64 / CELLS : 1;        // visibilities per wave step
-    constexpr int PASSES = (CELLS + 63) / 64;
+    constexpr int P = ALPHA;                                   // plane slots (batch size <= alpha)
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *acc = reinterpret_cast<C *>(smem_raw);                 // [P][16][kAccStride]
-    R *s_real = reinterpret_cast<R *>(acc + a.P * kAccPlane);  // [REALS][CH]
-    int *s_int = reinterpret_cast<int *>(s_real + ST::REALS * CH);   // [INTS][CH]
-    R *s_dre = s_real, *s_dim = s_real + CH;
-    R *s_ku = s_real + 2 * CH, *s_kv = s_ku + ALPHA * CH, *s_kw = s_kv + ALPHA * CH;   // [ALPHA][CH]
-    int *s_la = s_int, *s_lb = s_int + CH, *s_pr = s_int + 2 * CH, *s_ko = s_int + 3 * CH;
+    R *s_kw = reinterpret_cast<R *>(smem_raw);                 // [CH][P] rotated w weights
+    R *s_ku = s_kw + CH * P;                                   // [ALPHA][CH]
+    R *s_kv = s_ku + CH * ALPHA;                               // [ALPHA][CH]
+    C *s_d = reinterpret_cast<C *>(s_kv + CH * ALPHA);         // [CH]
+    int2 *s_anc = reinterpret_cast<int2 *>(s_d + CH);          // [CH] (la0, lb0)
 
     const Geom &g = a.g;
     const int ntiles = g.ntu * g.ntv;
@@ -76,7 +68,8 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
     if (tile < 0) return;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < a.P * kAccPlane; e += blockDim.x) acc[e] = cmake<C>((R)0, (R)0);
+    const int qa = (wave >> 1) * 8, qb = (wave & 1) * 8;       // quadrant origin
+    const int la = qa + (lane >> 3), lb = qb + (lane & 7);     // this lane's cell
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
     // the four contributing bins as one concatenated list
@@ -96,96 +89,86 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
         total += n;
         b_end[nb] = total;
     }
-    __syncthreads();
+    R acc_re[P], acc_im[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) acc_re[r] = acc_im[r] = (R)0;
+
     for (uint32_t base = 0; base < total; base += CH) {
         // ---- phase 1: one thread per visibility -------------------------
         if (tid < CH) {
             const uint32_t pos = base + tid;
-            int pr = 0;                                   // empty plane range
+            int2 anc = make_int2(1 << 20, 1 << 20);               // far away: touches nothing
             if (pos < total) {
                 int nb = pos < b_end[0] ? 0 : pos < b_end[1] ? 1 : pos < b_end[2] ? 2 : 3;
                 const uint32_t s = b_s0[nb] + (pos - (nb ? b_end[nb - 1] : 0u));
                 const uint32_t idx = a.order[s];
-                const int64_t r = idx / g.n_chan;
-                const int64_t c = idx - r * g.n_chan;
+                const uint32_t r = idx / (uint32_t)g.n_chan;
+                const uint32_t c = idx - r * (uint32_t)g.n_chan;
                 const VisCoord vc =
-                    vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
+                    vis_coord(a.uvw[3 * (int64_t)r], a.uvw[3 * (int64_t)r + 1], a.uvw[3 * (int64_t)r + 2],
+                              a.scale[c], g);
                 int la0 = vc.iu - A * kTileCells;
                 int lb0 = vc.iv - B * kTileCells;
                 if (la0 > g.nu / 2) la0 -= g.nu;
                 if (lb0 > g.nv / 2) lb0 -= g.nv;
+                anc = make_int2(la0, lb0);
                 C d = a.vis[idx];
                 if (a.wgt) d = cscale(d, a.wgt[idx]);
                 if (vc.flip) d.y = -d.y;
+                s_d[tid] = d;
                 R ku[ALPHA], kv[ALPHA], kw[ALPHA];
                 kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
                 kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
-                int p0, p1;
-                if (g.do_w) {
-                    kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
-                    p0 = max(vc.iw, j_lo) - j_lo;
-                    p1 = min(vc.iw + ALPHA, j_hi) - j_lo;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
-                    p0 = 0;
-                    p1 = 1;
-                }
-                if (p1 < p0) p1 = p0;
-                pr = p0 | (p1 << 16);
-                s_la[tid] = la0;
-                s_lb[tid] = lb0;
-                s_ko[tid] = j_lo - vc.iw;                  // kw index = p + kofs
-                s_dre[tid] = d.x;
-                s_dim[tid] = d.y;
 #pragma unroll
                 for (int i = 0; i < ALPHA; ++i) {
                     s_ku[i * CH + tid] = ku[i];
                     s_kv[i * CH + tid] = kv[i];
-                    s_kw[i * CH + tid] = kw[i];
+                }
+                // plane slot r holds plane j_lo + r; kernel index j - iw
+                if (g.do_w) {
+                    kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+                    const int sh = j_lo - vc.iw;                   // kernel index of slot 0
+#pragma unroll
+                    for (int rr = 0; rr < P; ++rr) {
+                        R wv = (R)0;
+#pragma unroll
+                        for (int i = 0; i < ALPHA; ++i) wv = (i == rr + sh && j_lo + rr < j_hi) ? kw[i] : wv;
+                        s_kw[tid * P + rr] = wv;
+                    }
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < P; ++rr) s_kw[tid * P + rr] = (R)(rr == 0);
                 }
             }
-            s_pr[tid] = pr;
+            s_anc[tid] = anc;
         }
         __syncthreads();
-        // ---- phase 2: wave owns planes p = wave (mod 4); lanes = cells ----
+        // ---- phase 2: lanes = cells of this wave's quadrant ----------------
         const int cnt = (int)min<uint32_t>((uint32_t)CH, total - base);
-        for (int v0 = 0; v0 < cnt; v0 += VPW) {
-#pragma unroll
-            for (int pass = 0; pass < PASSES; ++pass) {
-                const int cl = CELLS <= 64 ? lane % CELLS : pass * 64 + lane;
-                const int v = CELLS <= 64 ? v0 + lane / CELLS : v0;
-                const bool lane_ok = (CELLS <= 64 ? lane < VPW * CELLS : cl < CELLS) && v < cnt;
-                if (!lane_ok) continue;
-                const int pr = s_pr[v];
-                const int p0 = pr & 0xffff, p1 = pr >> 16;
-                int p = p0 + ((wave - p0) & (kGridWaves - 1));   // first plane of this wave
-                if (p >= p1) continue;
-                const int i = cl / ALPHA, k = cl - (cl / ALPHA) * ALPHA;
-                const int la = s_la[v] + i, lb = s_lb[v] + k;
-                if (la < 0 || la >= kTileCells || lb < 0 || lb >= kTileCells) continue;
+        for (int v = 0; v < cnt; ++v) {
+            const int2 anc = s_anc[v];
+            // footprint [la0, la0 + alpha) x [lb0, lb0 + alpha) against the quadrant (uniform test)
+            if (anc.x > qa + 7 || anc.x + ALPHA <= qa || anc.y > qb + 7 || anc.y + ALPHA <= qb) continue;
+            const int i = la - anc.x, k = lb - anc.y;
+            if (i >= 0 && i < ALPHA && k >= 0 && k < ALPHA) {
                 const R wuv = s_ku[i * CH + v] * s_kv[k * CH + v];
-                const R fr = s_dre[v] * wuv, fi = s_dim[v] * wuv;
-                const int ko = s_ko[v];
-                C *cellp = acc + la * kAccStride + lb;
-                for (; p < p1; p += kGridWaves) {
-                    const R kwv = s_kw[(p + ko) * CH + v];
-                    C cur = cellp[p * kAccPlane];
-                    cur.x += fr * kwv;
-                    cur.y += fi * kwv;
-                    cellp[p * kAccPlane] = cur;
+                const C d = s_d[v];
+                const R fr = d.x * wuv, fi = d.y * wuv;
+#pragma unroll
+                for (int r = 0; r < P; ++r) {
+                    const R kwv = s_kw[v * P + r];
+                    acc_re[r] += fr * kwv;
+                    acc_im[r] += fi * kwv;
                 }
             }
         }
         __syncthreads();
     }
     const int np = j_hi - j_lo;
-    for (int e = tid; e < np * kTileArea; e += blockDim.x) {
-        const int p = e / kTileArea, cell = e - p * kTileArea;
-        const int la = cell / kTileCells, lb = cell - la * kTileCells;
-        const int64_t off = ((int64_t)p * g.nu + (A * kTileCells + la)) * g.nv + (B * kTileCells + lb);
-        G[off] = acc[p * kAccPlane + la * kAccStride + lb];
-    }
+    const int64_t cell_off = (int64_t)(A * kTileCells + la) * g.nv + (B * kTileCells + lb);
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+        if (r < np) G[(int64_t)r * g.nu * g.nv + cell_off] = cmake<C>(acc_re[r], acc_im[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,12 +178,12 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
 // its visibilities and adds the batch's partial sum to its accumulator.
 // ---------------------------------------------------------------------------
 template <typename R, int ALPHA>
-__global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, const Cx<R> *__restrict__ G,
+__global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, const Cx<R> *__restrict__ G,
                                                 Cx<R> *__restrict__ visacc) {
     using C = Cx<R>;
     constexpr int W = kTileCells + ALPHA - 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *st = reinterpret_cast<C *>(smem_raw);
+    C *st = reinterpret_cast<C *>(smem_raw);                  // [PD][W][W]
     const Geom &g = a.g;
     const int ntiles = g.ntu * g.ntv;
     const int tile = xcd_remap(blockIdx.x, ntiles);
@@ -213,59 +196,67 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, const Cx<R>
     const int tid = threadIdx.x;
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
-    const int np = j_hi - j_lo;
-    for (int e = tid; e < np * W * W; e += blockDim.x) {
-        const int p = e / (W * W), cell = e - p * (W * W);
-        const int ra = cell / W, rb = cell - ra * W;
-        int ga = A * kTileCells + ra;
-        int gb = B * kTileCells + rb;
-        if (ga >= g.nu) ga -= g.nu;
-        if (gb >= g.nv) gb -= g.nv;
-        st[e] = G[((int64_t)p * g.nu + ga) * g.nv + gb];
-    }
-    __syncthreads();
-    for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
-        const uint32_t idx = a.order[s];
-        const int64_t r = idx / g.n_chan;
-        const int64_t c = idx - r * g.n_chan;
-        const VisCoord vc = vis_coord(a.uvw[3 * r], a.uvw[3 * r + 1], a.uvw[3 * r + 2], a.scale[c], g);
-        const int la0 = vc.iu - A * kTileCells;   // in [0, 16) by the index
-        const int lb0 = vc.iv - B * kTileCells;
-        if (la0 < 0 || la0 >= kTileCells || lb0 < 0 || lb0 >= kTileCells) continue;
-        R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-        kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
-        kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
-        if (g.do_w) {
-            kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
-        } else {
-#pragma unroll
-            for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
+    // planes are staged PD at a time (tile + halo of PD planes in LDS)
+    for (int g0 = j_lo; g0 < j_hi; g0 += PD) {
+        const int g1 = min(g0 + PD, j_hi);
+        const int np = g1 - g0;
+        for (int e = tid; e < np * W * W; e += blockDim.x) {
+            const int p = e / (W * W), cell = e - p * (W * W);
+            const int ra = cell / W, rb = cell - ra * W;
+            int ga = A * kTileCells + ra;
+            int gb = B * kTileCells + rb;
+            if (ga >= g.nu) ga -= g.nu;
+            if (gb >= g.nv) gb -= g.nv;
+            st[e] = G[((int64_t)(g0 - j_lo + p) * g.nu + ga) * g.nv + gb];
         }
-        const int nplanes_vis = g.do_w ? ALPHA : 1;
-        R sre = 0, sim = 0;
+        __syncthreads();
+        for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
+            const uint32_t idx = a.order[s];
+            const uint32_t r = idx / (uint32_t)g.n_chan;
+            const uint32_t c = idx - r * (uint32_t)g.n_chan;
+            const VisCoord vc = vis_coord(a.uvw[3 * (int64_t)r], a.uvw[3 * (int64_t)r + 1],
+                                          a.uvw[3 * (int64_t)r + 2], a.scale[c], g);
+            const int la0 = vc.iu - A * kTileCells;   // in [0, 16) by the index
+            const int lb0 = vc.iv - B * kTileCells;
+            if (la0 < 0 || la0 >= kTileCells || lb0 < 0 || lb0 >= kTileCells) continue;
+            const int jw0 = g.do_w ? max(vc.iw, g0) : g0;
+            const int jw1 = g.do_w ? min(vc.iw + ALPHA, g1) : g1;
+            if (jw0 >= jw1) continue;
+            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+            kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
+            kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+            if (g.do_w) {
+                kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+            } else {
 #pragma unroll
-        for (int jw = 0; jw < ALPHA; ++jw) {
-            const int j = vc.iw + jw;
-            if (jw >= nplanes_vis || j < j_lo || j >= j_hi) continue;
-            const C *pl = st + (j - j_lo) * (W * W) + la0 * W + lb0;
-            R pre = 0, pim = 0;
-#pragma unroll
-            for (int i = 0; i < ALPHA; ++i) {
-                R rre = 0, rim = 0;
-#pragma unroll
-                for (int k = 0; k < ALPHA; ++k) {
-                    const C v = pl[i * W + k];
-                    rre += kv[k] * v.x;
-                    rim += kv[k] * v.y;
-                }
-                pre += ku[i] * rre;
-                pim += ku[i] * rim;
+                for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
             }
-            sre += kw[jw] * pre;
-            sim += kw[jw] * pim;
+            R sre = 0, sim = 0;
+#pragma unroll
+            for (int jw = 0; jw < ALPHA; ++jw) {
+                const int j = (g.do_w ? vc.iw : g0) + jw;
+                if (j < jw0 || j >= jw1) continue;
+                const C *pl = st + (j - g0) * (W * W) + la0 * W + lb0;
+                R pre = 0, pim = 0;
+#pragma unroll
+                for (int i = 0; i < ALPHA; ++i) {
+                    R rre = 0, rim = 0;
+#pragma unroll
+                    for (int k = 0; k < ALPHA; ++k) {
+                        const C v = pl[i * W + k];
+                        rre += kv[k] * v.x;
+                        rim += kv[k] * v.y;
+                    }
+                    pre += ku[i] * rre;
+                    pim += ku[i] * rim;
+                }
+                sre += kw[jw] * pre;
+                sim += kw[jw] * pim;
+            }
+            C old = visacc[s];
+            visacc[s] = cmake<C>(old.x + sre, old.y + sim);
         }
-        C old = visacc[s];
-        visacc[s] = cmake<C>(old.x + sre, old.y + sim);
+        __syncthreads();
     }
 }
 

@@ -422,13 +422,12 @@ int plan_build(wg_plan *p) {
     // (FP32 <= 12288 values = 512 threads x kFftMaxC, FP64 <= 6144 = 256 x kFftMaxC)
     p->k_cols = 1;
     while (p->k_cols < 8 && (size_t)g.nu * (2 * p->k_cols) * sc <= 96 * 1024) p->k_cols *= 2;
-    // planes per batch: gridder accumulators P * 320 * sc <= 64 KB (beside its
-    // visibility staging), degridder staging P * (16 + alpha - 1)^2 * sc <= 72 KB
-    const int wst = kTileCells + p->alpha - 1;
-    int pmax = (int)std::min<size_t>(64 * 1024 / (kAccPlane * sc), 72 * 1024 / ((size_t)wst * wst * sc));
-    pmax = std::max(1, std::min(pmax, 32));
-    p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, pmax) : pmax;
+    // planes per batch: the gridder keeps one register accumulator per plane
+    // of the batch and lane, P = alpha (a visibility's alpha planes then meet
+    // at most two batches); the degridder stages P planes of tile + halo.
+    p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, p->alpha) : p->alpha;
     p->P = std::min(p->P, g.nw);
+    (void)sc;
     p->NJ = (g.nw + p->P - 1) / p->P;
     make_fft_desc(g.nu, p->fft_u);
     make_fft_desc(g.nv, p->fft_v);
@@ -525,7 +524,7 @@ template <typename R, int ALPHA> struct Launch {
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, hipStream_t st) {
         const int nt = p->g.ntu * p->g.ntv;
         const int nb = ((nt + 7) / 8) * 8;
-        const size_t lds = (size_t)p->P * kAccPlane * sizeof(Cx<R>) + GridStage<R, ALPHA>::bytes;
+        const size_t lds = GridStage<R, ALPHA>::bytes;
         hipLaunchKernelGGL((k_grid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G);
     }
     static void degrid(const wg_plan *p, const VisArgs<R> &va, int J, const Cx<R> *G, Cx<R> *vacc,
@@ -533,8 +532,9 @@ template <typename R, int ALPHA> struct Launch {
         const int nt = p->g.ntu * p->g.ntv;
         const int nb = ((nt + 7) / 8) * 8;
         const int W = kTileCells + ALPHA - 1;
-        const size_t lds = (size_t)p->P * W * W * sizeof(Cx<R>);
-        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G, vacc);
+        const int pd = std::max(1, std::min(p->P, (int)(72 * 1024 / ((size_t)W * W * sizeof(Cx<R>)))));
+        const size_t lds = (size_t)pd * W * W * sizeof(Cx<R>);
+        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, pd, G, vacc);
     }
 };
 
