@@ -304,7 +304,10 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     using C = Cx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int q0 = blockIdx.x * K;
+    // neighbouring column blocks share cache lines: keep them on one XCD
+    const int cb = xcd_remap(blockIdx.x, (pg.npix_y + K - 1) / K);
+    if (cb < 0) return;
+    const int q0 = cb * K;
     const int kk = min(K, pg.npix_y - q0);
     const int h = pg.npix_x / 2;
     for (int p = 0; p < np; ++p) {
@@ -392,7 +395,10 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
     using C = Cx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int b0 = blockIdx.x * K;
+    // neighbouring column blocks share cache lines: keep them on one XCD
+    const int cb = xcd_remap(blockIdx.x, (pg.nv + K - 1) / K);
+    if (cb < 0) return;
+    const int b0 = cb * K;
     const int p = blockIdx.y;
     const int kk = min(K, pg.nv - b0);
     const int h = pg.npix_x / 2;

@@ -561,7 +561,7 @@ template <typename R, int NTH> struct FftLaunch {
     static void cols_grid(const wg_plan *p, const Cx<R> *T, R *acc, const PassGeom &pg, int j_lo, int np,
                           hipStream_t st) {
         const int K = p->k_cols;
-        const int nb = (p->g.npix_y + K - 1) / K;
+        const int nb = ((p->g.npix_y + K - 1) / K + 7) / 8 * 8;
         hipLaunchKernelGGL((k_cols_grid<R, NTH>), dim3(nb), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>), st, T,
                            acc, p->nm1, pg, K, j_lo, np, p->fft_u, (const Cx<R> *)p->tw_u);
     }
@@ -573,7 +573,7 @@ template <typename R, int NTH> struct FftLaunch {
     static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
                             hipStream_t st) {
         const int K = p->k_cols;
-        const int nb = (p->g.nv + K - 1) / K;
+        const int nb = ((p->g.nv + K - 1) / K + 7) / 8 * 8;
         hipLaunchKernelGGL((k_cols_degrid<R, NTH>), dim3(nb, np), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>),
                            st, T, G, pg, K, p->fft_u, (const Cx<R> *)p->tw_u);
     }
