@@ -119,6 +119,17 @@ __device__ __forceinline__ void kernel_values(double offset, double half, const 
     }
 }
 
+// Same, from the precomputed local variable z.
+template <int ALPHA, typename R>
+__device__ __forceinline__ void kernel_values_z(R z, const R *__restrict__ coef, int degree, R out[ALPHA]) {
+#pragma unroll
+    for (int i = 0; i < ALPHA; ++i) out[i] = coef[degree * ALPHA + i];
+    for (int d = degree - 1; d >= 0; --d) {
+#pragma unroll
+        for (int i = 0; i < ALPHA; ++i) out[i] = out[i] * z + coef[d * ALPHA + i];
+    }
+}
+
 // blockIdx -> work-item remap that keeps neighbouring tiles on one XCD:
 // workgroups are dealt round-robin over the 8 XCDs, so give XCD x the
 // contiguous range [x * per, (x + 1) * per).  Returns -1 for padding blocks.

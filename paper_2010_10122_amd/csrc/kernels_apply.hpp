@@ -11,12 +11,13 @@ constexpr int kTileCells = 16;            // uv tile edge (cells)
 constexpr int kTileArea = kTileCells * kTileCells;
 
 // Arguments shared by the gridder and the degridder.
+// Per selected visibility, in sorted order (built once per plan): the
+// kernel-local coordinates z in [-1, 1) of the u, v and w kernels and the
+// anchor cell/plane: anc.x = i_u | i_v << 16, anc.y = i_w | fold << 31.
 template <typename R> struct VisArgs {
-    const double *uvw;          // [n_rows][3]
-    const double *scale;        // [n_chan] freq / c
-    const Cx<R> *vis;           // gridder input  [n_rows][n_chan]
-    const R *wgt;               // optional [n_rows][n_chan]
-    const uint32_t *order;      // sorted visibility order
+    const R *z;                 // [n_active][3] (z_u, z_v, z_w)
+    const int2 *anc;            // [n_active]
+    const Cx<R> *vsorted;       // gridder input in sorted order, weighted and unfolded
     const uint32_t *tab_lo;     // [tiles][NJ+1], shift alpha-1
     const uint32_t *tab_hi;     // [tiles][NJ+1], shift 0
     const R *coef;              // [degree+1][alpha] kernel polynomial
@@ -44,23 +45,26 @@ template <typename R> struct VisArgs {
 // each other and need no atomics.
 // ---------------------------------------------------------------------------
 template <typename R, int ALPHA> struct GridStage {
-    static constexpr int CH = (sizeof(R) == 8 && ALPHA >= 12) ? 128 : 256;   // visibilities per chunk
-    static constexpr int REALS = 2 + 3 * ALPHA;    // d.re, d.im, ku[alpha], kv[alpha], kw slots[alpha]
-    static constexpr size_t bytes = (size_t)CH * (2 * sizeof(int) + REALS * sizeof(R));
+    static constexpr int CH = 256;                 // visibilities per chunk (one per phase-1 thread)
+    static constexpr int S = CH + 1;               // + one zero-weight slot used as padding
+    static constexpr size_t bytes = (size_t)S * (3 * ALPHA * sizeof(R) + sizeof(Cx<R>) + sizeof(int2)) +
+                                    4 * CH * sizeof(uint16_t) + 64;
 };
 
 template <typename R, int ALPHA>
 __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__restrict__ G) {
     using C = Cx<R>;
     using ST = GridStage<R, ALPHA>;
-    constexpr int CH = ST::CH;
+    constexpr int CH = ST::CH, S = ST::S;
     constexpr int P = ALPHA;                                   // plane slots (batch size <= alpha)
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *s_kw = reinterpret_cast<R *>(smem_raw);                 // [CH][P] rotated w weights
-    R *s_ku = s_kw + CH * P;                                   // [ALPHA][CH]
-    R *s_kv = s_ku + CH * ALPHA;                               // [ALPHA][CH]
-    C *s_d = reinterpret_cast<C *>(s_kv + CH * ALPHA);         // [CH]
-    int2 *s_anc = reinterpret_cast<int2 *>(s_d + CH);          // [CH] (la0, lb0)
+    R *s_kw = reinterpret_cast<R *>(smem_raw);                 // [S][P] rotated w weights
+    R *s_ku = s_kw + S * P;                                    // [S][ALPHA]
+    R *s_kv = s_ku + S * ALPHA;                                // [S][ALPHA]
+    C *s_d = reinterpret_cast<C *>(s_kv + S * ALPHA);          // [S]
+    int2 *s_anc = reinterpret_cast<int2 *>(s_d + S);           // [S] (la0, lb0)
+    uint16_t *s_list = reinterpret_cast<uint16_t *>(s_anc + S);   // [4][CH] per-quadrant lists
+    int *s_cnt = reinterpret_cast<int *>(s_list + 4 * CH);     // [4 quadrants][4 waves]
 
     const Geom &g = a.g;
     const int ntiles = g.ntu * g.ntv;
@@ -89,69 +93,98 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
         total += n;
         b_end[nb] = total;
     }
+    // the padding slot contributes nothing
+    if (tid == 0) {
+        s_d[CH] = cmake<C>((R)0, (R)0);
+        s_anc[CH] = make_int2(1 << 20, 1 << 20);
+    }
+    if (tid < P) s_kw[CH * P + tid] = (R)0;
+    if (tid < ALPHA) {
+        s_ku[CH * ALPHA + tid] = (R)0;
+        s_kv[CH * ALPHA + tid] = (R)0;
+    }
     R acc_re[P], acc_im[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) acc_re[r] = acc_im[r] = (R)0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
 
     for (uint32_t base = 0; base < total; base += CH) {
         // ---- phase 1: one thread per visibility -------------------------
-        if (tid < CH) {
-            const uint32_t pos = base + tid;
-            int2 anc = make_int2(1 << 20, 1 << 20);               // far away: touches nothing
-            if (pos < total) {
-                int nb = pos < b_end[0] ? 0 : pos < b_end[1] ? 1 : pos < b_end[2] ? 2 : 3;
-                const uint32_t s = b_s0[nb] + (pos - (nb ? b_end[nb - 1] : 0u));
-                const uint32_t idx = a.order[s];
-                const uint32_t r = idx / (uint32_t)g.n_chan;
-                const uint32_t c = idx - r * (uint32_t)g.n_chan;
-                const VisCoord vc =
-                    vis_coord(a.uvw[3 * (int64_t)r], a.uvw[3 * (int64_t)r + 1], a.uvw[3 * (int64_t)r + 2],
-                              a.scale[c], g);
-                int la0 = vc.iu - A * kTileCells;
-                int lb0 = vc.iv - B * kTileCells;
-                if (la0 > g.nu / 2) la0 -= g.nu;
-                if (lb0 > g.nv / 2) lb0 -= g.nv;
-                anc = make_int2(la0, lb0);
-                C d = a.vis[idx];
-                if (a.wgt) d = cscale(d, a.wgt[idx]);
-                if (vc.flip) d.y = -d.y;
-                s_d[tid] = d;
-                R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-                kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
-                kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+        const uint32_t pos = base + tid;
+        int qmask = 0;
+        if (pos < total) {
+            int nb = pos < b_end[0] ? 0 : pos < b_end[1] ? 1 : pos < b_end[2] ? 2 : 3;
+            const uint32_t s = b_s0[nb] + (pos - (nb ? b_end[nb - 1] : 0u));
+            const int2 an = a.anc[s];
+            const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
+            int la0 = iu - A * kTileCells;
+            int lb0 = iv - B * kTileCells;
+            if (la0 > g.nu / 2) la0 -= g.nu;
+            if (lb0 > g.nv / 2) lb0 -= g.nv;
+            s_anc[tid] = make_int2(la0, lb0);
 #pragma unroll
-                for (int i = 0; i < ALPHA; ++i) {
-                    s_ku[i * CH + tid] = ku[i];
-                    s_kv[i * CH + tid] = kv[i];
-                }
-                // plane slot r holds plane j_lo + r; kernel index j - iw
-                if (g.do_w) {
-                    kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
-                    const int sh = j_lo - vc.iw;                   // kernel index of slot 0
-#pragma unroll
-                    for (int rr = 0; rr < P; ++rr) {
-                        R wv = (R)0;
-#pragma unroll
-                        for (int i = 0; i < ALPHA; ++i) wv = (i == rr + sh && j_lo + rr < j_hi) ? kw[i] : wv;
-                        s_kw[tid * P + rr] = wv;
-                    }
-                } else {
-#pragma unroll
-                    for (int rr = 0; rr < P; ++rr) s_kw[tid * P + rr] = (R)(rr == 0);
-                }
+            for (int q = 0; q < 4; ++q) {
+                const int oa = (q >> 1) * 8, ob = (q & 1) * 8;
+                if (la0 <= oa + 7 && la0 + ALPHA > oa && lb0 <= ob + 7 && lb0 + ALPHA > ob) qmask |= 1 << q;
             }
-            s_anc[tid] = anc;
+            s_d[tid] = a.vsorted[s];
+            const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
+            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+            kernel_values_z<ALPHA, R>(zu, a.coef, a.degree, ku);
+            kernel_values_z<ALPHA, R>(zv, a.coef, a.degree, kv);
+#pragma unroll
+            for (int i = 0; i < ALPHA; ++i) {
+                s_ku[tid * ALPHA + i] = ku[i];
+                s_kv[tid * ALPHA + i] = kv[i];
+            }
+            // plane slot r holds plane j_lo + r; kernel index j - iw
+            if (g.do_w) {
+                kernel_values_z<ALPHA, R>(zw, a.coef, a.degree, kw);
+                const int sh = j_lo - iw;                      // kernel index of slot 0
+#pragma unroll
+                for (int rr = 0; rr < P; ++rr) {
+                    R wv = (R)0;
+#pragma unroll
+                    for (int i = 0; i < ALPHA; ++i) wv = (i == rr + sh && j_lo + rr < j_hi) ? kw[i] : wv;
+                    s_kw[tid * P + rr] = wv;
+                }
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < P; ++rr) s_kw[tid * P + rr] = (R)(rr == 0);
+            }
+        }
+        // per-quadrant lists: wave-level ballots, then offsets across waves
+        unsigned long long bal[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bal[q] = __ballot((qmask >> q) & 1);
+            if (lane == 0) s_cnt[q * 4 + wave] = (int)__popcll(bal[q]);
         }
         __syncthreads();
-        // ---- phase 2: lanes = cells of this wave's quadrant ----------------
-        const int cnt = (int)min<uint32_t>((uint32_t)CH, total - base);
-        for (int v = 0; v < cnt; ++v) {
-            const int2 anc = s_anc[v];
-            // footprint [la0, la0 + alpha) x [lb0, lb0 + alpha) against the quadrant (uniform test)
-            if (anc.x > qa + 7 || anc.x + ALPHA <= qa || anc.y > qb + 7 || anc.y + ALPHA <= qb) continue;
-            const int i = la - anc.x, k = lb - anc.y;
-            if (i >= 0 && i < ALPHA && k >= 0 && k < ALPHA) {
-                const R wuv = s_ku[i * CH + v] * s_kv[k * CH + v];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if ((qmask >> q) & 1) {
+                int off = 0;
+                for (int w = 0; w < wave; ++w) off += s_cnt[q * 4 + w];
+                s_list[q * CH + off + (int)__popcll(bal[q] & lt)] = (uint16_t)tid;
+            }
+        }
+        __syncthreads();
+        // ---- phase 2: this wave's quadrant, lanes = cells, 4 visibilities a step
+        const int n = s_cnt[wave * 4 + 0] + s_cnt[wave * 4 + 1] + s_cnt[wave * 4 + 2] + s_cnt[wave * 4 + 3];
+        const uint16_t *lst = s_list + wave * CH;
+        for (int j = 0; j < n; j += 4) {
+            int vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) vv[u] = (j + u < n) ? (int)lst[j + u] : CH;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = vv[u];
+                const int2 an = s_anc[v];
+                const int i = la - an.x, k = lb - an.y;
+                const bool act = (unsigned)i < (unsigned)ALPHA && (unsigned)k < (unsigned)ALPHA;
+                const int ic = act ? i : 0, kc = act ? k : 0;
+                const R wuv = act ? s_ku[v * ALPHA + ic] * s_kv[v * ALPHA + kc] : (R)0;
                 const C d = s_d[v];
                 const R fr = d.x * wuv, fi = d.y * wuv;
 #pragma unroll
@@ -211,22 +244,20 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
         }
         __syncthreads();
         for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
-            const uint32_t idx = a.order[s];
-            const uint32_t r = idx / (uint32_t)g.n_chan;
-            const uint32_t c = idx - r * (uint32_t)g.n_chan;
-            const VisCoord vc = vis_coord(a.uvw[3 * (int64_t)r], a.uvw[3 * (int64_t)r + 1],
-                                          a.uvw[3 * (int64_t)r + 2], a.scale[c], g);
-            const int la0 = vc.iu - A * kTileCells;   // in [0, 16) by the index
-            const int lb0 = vc.iv - B * kTileCells;
+            const int2 an = a.anc[s];
+            const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
+            const int la0 = iu - A * kTileCells;   // in [0, 16) by the index
+            const int lb0 = iv - B * kTileCells;
             if (la0 < 0 || la0 >= kTileCells || lb0 < 0 || lb0 >= kTileCells) continue;
-            const int jw0 = g.do_w ? max(vc.iw, g0) : g0;
-            const int jw1 = g.do_w ? min(vc.iw + ALPHA, g1) : g1;
+            const int jw0 = g.do_w ? max(iw, g0) : g0;
+            const int jw1 = g.do_w ? min(iw + ALPHA, g1) : g1;
             if (jw0 >= jw1) continue;
+            const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values<ALPHA, R>(vc.ou, g.half, a.coef, a.degree, ku);
-            kernel_values<ALPHA, R>(vc.ov, g.half, a.coef, a.degree, kv);
+            kernel_values_z<ALPHA, R>(zu, a.coef, a.degree, ku);
+            kernel_values_z<ALPHA, R>(zv, a.coef, a.degree, kv);
             if (g.do_w) {
-                kernel_values<ALPHA, R>(vc.ow, g.half, a.coef, a.degree, kw);
+                kernel_values_z<ALPHA, R>(zw, a.coef, a.degree, kw);
             } else {
 #pragma unroll
                 for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
@@ -234,7 +265,7 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
             R sre = 0, sim = 0;
 #pragma unroll
             for (int jw = 0; jw < ALPHA; ++jw) {
-                const int j = (g.do_w ? vc.iw : g0) + jw;
+                const int j = (g.do_w ? iw : g0) + jw;
                 if (j < jw0 || j >= jw1) continue;
                 const C *pl = st + (j - g0) * (W * W) + la0 * W + lb0;
                 R pre = 0, pim = 0;
@@ -440,17 +471,30 @@ __global__ void k_fill_zero(T *__restrict__ p, int64_t n) {
 // scatter from sorted order to [n_rows][n_chan].
 template <typename R>
 __global__ void k_degrid_finish(const Cx<R> *__restrict__ visacc, const uint32_t *__restrict__ order,
-                                const double *__restrict__ uvw, const double *__restrict__ scale,
-                                const R *__restrict__ wgt, int64_t n_active, int64_t n_chan, int do_w,
+                                const int2 *__restrict__ anc, const R *__restrict__ wgt, int64_t n_active,
                                 Cx<R> *__restrict__ vis) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
          s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t idx = order[s];
-        const int64_t r = idx / n_chan, c = idx - (idx / n_chan) * n_chan;
         Cx<R> v = visacc[s];
-        if (do_w && uvw[3 * r + 2] * scale[c] < 0.0) v.y = -v.y;
+        if (anc[s].y < 0) v.y = -v.y;
         if (wgt) v = cscale(v, wgt[idx]);
         vis[idx] = v;
+    }
+}
+
+// Gridding input in sorted order: weighted, and conjugated where folded.
+template <typename R>
+__global__ void k_gather_vis(const Cx<R> *__restrict__ vis, const R *__restrict__ wgt,
+                             const uint32_t *__restrict__ order, const int2 *__restrict__ anc, int64_t n_active,
+                             Cx<R> *__restrict__ vsorted) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = order[s];
+        Cx<R> v = vis[idx];
+        if (wgt) v = cscale(v, wgt[idx]);
+        if (anc[s].y < 0) v.y = -v.y;
+        vsorted[s] = v;
     }
 }
 

@@ -201,6 +201,27 @@ __global__ void k_fill_tab(const unsigned long long *__restrict__ keys, int64_t 
     }
 }
 
+// ---- per sorted visibility: kernel-local coordinates and anchors ------------
+// z = 2 (first cell - coordinate + alpha/2) - 1 in [-1, 1) for u, v and w
+// (the shared local variable of the alpha polynomial pieces), anchors packed
+// as anc.x = i_u | i_v << 16, anc.y = i_w | fold << 31.
+template <typename R>
+__global__ void k_vis_prep(const double *__restrict__ uvw, const double *__restrict__ scale,
+                           const uint32_t *__restrict__ order, int64_t n_active, Geom g, R *__restrict__ z,
+                           int2 *__restrict__ anc) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t idx = order[s];
+        const int64_t r = idx / g.n_chan;
+        const int64_t c = idx - r * g.n_chan;
+        const VisCoord vc = vis_coord(uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], scale[c], g);
+        z[3 * s] = (R)(2.0 * (vc.ou + g.half) - 1.0);
+        z[3 * s + 1] = (R)(2.0 * (vc.ov + g.half) - 1.0);
+        z[3 * s + 2] = (R)(g.do_w ? 2.0 * (vc.ow + g.half) - 1.0 : 0.0);
+        anc[s] = make_int2(vc.iu | (vc.iv << 16), vc.iw | (vc.flip ? (int)0x80000000u : 0));
+    }
+}
+
 // ---- n - 1 and the correction 1 / (n Psi) per pixel ------------------------
 // Psi = psi(p'/N_u) psi(q'/N_v) psi((n-1) dw) (Sect. 2), psi by quadrature with
 // precomputed nodes t_i and weights wphi_i = w_i phi(t_i) on [0, alpha/2].

@@ -214,6 +214,8 @@ struct wg_plan {
     unsigned long long *keys = nullptr;
     uint32_t *order = nullptr;
     uint32_t *tab_lo = nullptr, *tab_hi = nullptr;
+    void *zc = nullptr;                // [n_active][3] R: kernel-local coordinates
+    int2 *anc = nullptr;               // [n_active] anchors and fold bit
     size_t index_bytes = 0;
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
@@ -494,7 +496,22 @@ int plan_build(wg_plan *p) {
     hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
                        p->keys, p->n_active, g.nw, p->P, p->NJ, 0, tab_n, p->tab_hi);
     LAUNCH_CHECK("k_fill_tab");
-    p->index_bytes = nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t);
+    // sorted per-visibility stream: kernel-local coordinates and anchors
+    const int64_t nact = std::max<int64_t>(p->n_active, 1);
+    p->zc = p->mem.get(nact * 3 * sr);
+    p->anc = (int2 *)p->mem.get(nact * sizeof(int2));
+    if (!p->zc || !p->anc) return WG_ENOMEM;
+    if (p->n_active > 0) {
+        if (d.precision == WG_F32)
+            hipLaunchKernelGGL(k_vis_prep<float>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 20)), dim3(256), 0,
+                               st, d.uvw, p->scale, p->order, p->n_active, g, (float *)p->zc, p->anc);
+        else
+            hipLaunchKernelGGL(k_vis_prep<double>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 20)), dim3(256),
+                               0, st, d.uvw, p->scale, p->order, p->n_active, g, (double *)p->zc, p->anc);
+        LAUNCH_CHECK("k_vis_prep");
+    }
+    p->index_bytes = nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t) +
+                     nact * (3 * sr + sizeof(int2));
     HIP_TRY(hipStreamSynchronize(st));
     p->mem.put(dpx);
     p->mem.put(dpy);
@@ -619,11 +636,9 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     const int64_t npix = (int64_t)g.npix_x * g.npix_y;
 
     VisArgs<R> va;
-    va.uvw = d.uvw;
-    va.scale = p->scale;
-    va.vis = gridding ? (const C *)in : nullptr;
-    va.wgt = (const R *)wgt;
-    va.order = p->order;
+    va.z = (const R *)p->zc;
+    va.anc = p->anc;
+    va.vsorted = vacc;              // gridding: the sorted input lives where degridding accumulates
     va.tab_lo = p->tab_lo;
     va.tab_hi = p->tab_hi;
     va.coef = (const R *)p->coef;
@@ -640,6 +655,11 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                                npix);
         }
         if (p->n_active > 0) {
+            {
+                ProfScope ps(WG_KIND_VIS, st);
+                hipLaunchKernelGGL(k_gather_vis<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
+                                   0, st, (const C *)in, (const R *)wgt, p->order, p->anc, p->n_active, vacc);
+            }
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
@@ -698,8 +718,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
             {
                 ProfScope ps(WG_KIND_VIS, st);
                 hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
-                                   0, st, vacc, p->order, d.uvw, p->scale, (const R *)wgt, p->n_active, d.n_chan,
-                                   g.do_w, (C *)out);
+                                   0, st, vacc, p->order, p->anc, (const R *)wgt, p->n_active, (C *)out);
             }
         }
     }
@@ -750,6 +769,8 @@ int wg_plan_destroy(wg_plan *p) {
     p->mem.put(p->order);
     p->mem.put(p->tab_lo);
     p->mem.put(p->tab_hi);
+    p->mem.put(p->zc);
+    p->mem.put(p->anc);
     delete p;
     return WG_OK;
 }
