@@ -166,3 +166,29 @@ def differentiation(seed=5, n_dumps=620, n_chan=4, npix=1024, n_src=100, noise_f
     sky = point_sources(rng, npix, npix, n_src)
     return dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
                 sky=sky, noise_frac=noise_frac, rng=rng, name=f"diff-{npix}^2")
+
+
+def serving_requests(seed=4, count=32, sizes=(512, 1024, 2048, 4096), nvis_range=(1e5, 2e7),
+                     epsilons=(1e-4, 1e-5, 1e-7, 1e-9), pixsize=10.0 * DEG / 2048, base=None):
+    """Request mix of the serving workload: image size uniform over ``sizes``;
+    visibility count log-uniform over ``nvis_range``, drawn as a contiguous
+    row range of the wide-field array (16 channels, fewer for small counts);
+    epsilon uniform over ``epsilons`` (FP32 where eps >= 1e-5, else FP64);
+    direction degrid/grid 50/50.  Returns (base workload, list of dicts)."""
+    rng = np.random.default_rng(seed)
+    if base is None:
+        base = wide_field(with_vis=False)
+    nrow_all, nch_all = base["uvw"].shape[0], len(base["freq"])
+    out = []
+    for rid in range(count):
+        npix = int(rng.choice(sizes))
+        nvis = int(10 ** rng.uniform(np.log10(nvis_range[0]), np.log10(nvis_range[1])))
+        nch = int(min(nch_all, max(1, nvis // 20000)))
+        nrow = int(min(nrow_all, max(1, nvis // nch)))
+        r0 = int(rng.integers(0, nrow_all - nrow + 1))
+        eps = float(rng.choice(epsilons))
+        out.append(dict(rid=rid, npix=npix, pixsize=pixsize, rows=(r0, r0 + nrow), nchan=nch, epsilon=eps,
+                        precision="f32" if eps >= 1e-5 else "f64",
+                        direction="degrid" if rng.random() < 0.5 else "grid",
+                        seed=int(rng.integers(0, 2 ** 31))))
+    return base, out
