@@ -70,7 +70,8 @@ typedef struct {
     int            do_wgridding; /* 0: w treated as zero (narrow field), else w-gridding */
     int            alpha;        /* 0 = automatic; else force kernel support (4,7,8,12,16) */
     double         sigma;        /* 0 = automatic; else force oversampling (table row)  */
-    int            planes_per_batch; /* 0 = automatic; w-planes processed per batch     */
+    int            planes_per_batch; /* 0 = automatic; w-planes processed per batch,
+                                        capped at alpha and at 8 (FP32) / 4 (FP64)      */
     void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
     wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
     wg_free_fn     free;
@@ -140,6 +141,8 @@ typedef struct {
     size_t  plan_bytes;       /* device bytes held by the plan                        */
     size_t  index_bytes;      /* of which visibility index                            */
     size_t  workspace_bytes;  /* per apply call                                       */
+    int64_t extra_items_grid; /* gridder work items beyond one per tile, all batches  */
+    int64_t extra_items_degrid;/* likewise for the degridder                          */
 } wg_plan_info_t;
 
 int    wg_plan_info(const wg_plan *plan, wg_plan_info_t *info);

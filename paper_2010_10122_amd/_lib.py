@@ -66,6 +66,8 @@ class PlanInfo(ctypes.Structure):
         ("plan_bytes", ctypes.c_size_t),
         ("index_bytes", ctypes.c_size_t),
         ("workspace_bytes", ctypes.c_size_t),
+        ("extra_items_grid", ctypes.c_int64),
+        ("extra_items_degrid", ctypes.c_int64),
     ]
 
 

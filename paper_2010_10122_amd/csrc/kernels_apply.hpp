@@ -9,6 +9,11 @@ namespace wg {
 
 constexpr int kTileCells = 16;            // uv tile edge (cells)
 constexpr int kTileArea = kTileCells * kTileCells;
+#ifndef WG_GRID_ITEM_CAP
+#define WG_GRID_ITEM_CAP 2048
+#endif
+constexpr int kGridItemCap = WG_GRID_ITEM_CAP;   // visibilities per gridder work item
+constexpr int kDegridItemCap = 2048;             // visibilities per degridder work item
 
 // Arguments shared by the gridder and the degridder.
 // Per selected visibility, in sorted order (built once per plan): the
@@ -29,51 +34,94 @@ template <typename R> struct VisArgs {
 
 // ---------------------------------------------------------------------------
 // Gridder (adjoint, eq. Rad2 before the FFT).  One workgroup owns one 16x16
-// tile of the grid for the P = alpha planes of batch J and accumulates every
-// visibility whose kernel footprint reaches the tile: those anchored in the
-// tile itself and in the three neighbouring tiles up/left (a footprint spans
-// at most alpha <= 16 cells).  No two workgroups write the same grid cell,
-// so the tile is flushed with plain stores, zeros included.
+// tile of the grid for the (at most PS) planes of batch J and accumulates
+// every visibility whose kernel footprint reaches the tile: those anchored in
+// the tile itself and in the three neighbouring tiles up/left (a footprint
+// spans at most alpha <= 16 cells).  No two workgroups write the same grid
+// cell, so the tile is flushed with plain stores, zeros included.
 //
-// Visibilities are taken in chunks.  Phase 1, one thread per visibility:
-// tile-relative anchor, weighted value, the u and v kernel values and the w
-// weights rotated onto the batch's plane slots go to LDS.  Phase 2: wave w
-// owns quadrant w (8 x 8 cells) of the tile, lane = cell, and holds that
-// cell's P plane accumulators in registers; for every staged visibility
-// whose footprint meets the quadrant it adds value * ku * kv * kw[slot] to
-// each slot.  Every LDS access in phase 2 is a read, so waves never wait on
-// each other and need no atomics.
+// Work is dealt in items of at most a fixed number of visibilities (the
+// uv coverage is far from uniform: a tile near the origin can hold a hundred
+// times the mean), so one launch is made of many similar workgroups.  A tile
+// whose list is longer is split over several items: the first writes the
+// grid planes, the others write partial tiles to scratch, and k_grid_reduce
+// adds those to the planes in item order, so the sum order is fixed.
+//
+// Visibilities are taken in chunks of CH.  Phase 1, one thread per
+// visibility: tile-relative anchor, weighted value, the u and v kernel values
+// (zero-padded by three cells on each side, so that any cell of a 4x4 region
+// the footprint meets indexes inside the padded row) and the w weights
+// rotated onto the batch's plane slots go to LDS, plus a 16-bit mask of the
+// 4x4 regions of the tile the footprint meets; per-region lists are built
+// with wave ballots.  Phase 2: wave w owns the four regions of rows
+// 4w..4w+3; its lanes form four groups of 16, one cell of the region each,
+// and the groups take four different visibilities of the region's list at a
+// time (so a footprint of alpha^2 cells keeps most lanes busy), each lane
+// holding its cell's PS plane accumulators for the four regions in
+// registers.  At the flush the four groups' partial sums are added with
+// cross-lane shuffles.  Every LDS access in phase 2 is a read, so waves never
+// wait on each other and need no atomics.
 // ---------------------------------------------------------------------------
-template <typename R, int ALPHA> struct GridStage {
+template <typename R, int ALPHA, int PS> struct GridStage {
     static constexpr int CH = 256;                 // visibilities per chunk (one per phase-1 thread)
-    static constexpr int S = CH + 1;               // + one zero-weight slot used as padding
-    static constexpr size_t bytes = (size_t)S * (3 * ALPHA * sizeof(R) + sizeof(Cx<R>) + sizeof(int2)) +
-                                    4 * CH * sizeof(uint16_t) + 64;
+    static constexpr int S = CH + 1;               // + one zero slot used as padding
+    static constexpr int KP = ALPHA + 6;           // padded kernel row
+    static constexpr int NKP = S * KP + 16;        // padded rows + zero tail for the padding slot
+    static constexpr int NREG = 16;                // 4x4-cell regions of a tile
+    static constexpr int LST = CH + 8;             // list capacity: entries + padding
+    static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
+    static constexpr size_t off_kv = al((size_t)NKP * sizeof(R));
+    static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(R));
+    static constexpr size_t off_d = al(off_kw + (size_t)S * PS * sizeof(R));
+    static constexpr size_t off_base = al(off_d + (size_t)S * sizeof(Cx<R>));
+    static constexpr size_t off_list = al(off_base + (size_t)S * sizeof(int2));
+    static constexpr size_t off_cnt = al(off_list + (size_t)NREG * LST * sizeof(uint16_t));
+    static constexpr size_t bytes = off_cnt + (size_t)NREG * 4 * sizeof(int);
 };
 
-template <typename R, int ALPHA>
-__global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__restrict__ G) {
+// Block -> work item.  Blocks [0, pad8(n_extra)) take the listed extra items
+// (heaviest tiles first in dispatch order, dealt round-robin over the XCDs);
+// the following blocks take the first item of every tile, (tile, 0, cap, -1),
+// in the XCD-contiguous tile order.  Returns false for padding blocks.
+__device__ __forceinline__ bool work_item(const int4 *__restrict__ extra, int n_extra, int ntiles, int cap,
+                                          int4 &item) {
+    const int pad = (n_extra + 7) & ~7;
+    const int b = (int)blockIdx.x;
+    if (b < pad) {
+        if (b >= n_extra) return false;
+        item = extra[b];
+        return true;
+    }
+    const int t = xcd_remap(b - pad, ntiles);
+    if (t < 0) return false;
+    item = make_int4(t, 0, cap, -1);
+    return true;
+}
+
+template <typename R, int ALPHA, int PS>
+__global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra,
+                                              int cap, Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
     using C = Cx<R>;
-    using ST = GridStage<R, ALPHA>;
-    constexpr int CH = ST::CH, S = ST::S;
-    constexpr int P = ALPHA;                                   // plane slots (batch size <= alpha)
+    using ST = GridStage<R, ALPHA, PS>;
+    constexpr int CH = ST::CH, KP = ST::KP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *s_kw = reinterpret_cast<R *>(smem_raw);                 // [S][P] rotated w weights
-    R *s_ku = s_kw + S * P;                                    // [S][ALPHA]
-    R *s_kv = s_ku + S * ALPHA;                                // [S][ALPHA]
-    C *s_d = reinterpret_cast<C *>(s_kv + S * ALPHA);          // [S]
-    int2 *s_anc = reinterpret_cast<int2 *>(s_d + S);           // [S] (la0, lb0)
-    uint16_t *s_list = reinterpret_cast<uint16_t *>(s_anc + S);   // [4][CH] per-quadrant lists
-    int *s_cnt = reinterpret_cast<int *>(s_list + 4 * CH);     // [4 quadrants][4 waves]
+    R *s_ku = reinterpret_cast<R *>(smem_raw);                         // [S][KP] + tail
+    R *s_kv = reinterpret_cast<R *>(smem_raw + ST::off_kv);            // [S][KP] + tail
+    R *s_kw = reinterpret_cast<R *>(smem_raw + ST::off_kw);            // [S][PS]
+    C *s_d = reinterpret_cast<C *>(smem_raw + ST::off_d);              // [S]
+    int2 *s_base = reinterpret_cast<int2 *>(smem_raw + ST::off_base);  // [S] row bases into s_ku / s_kv
+    uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);   // [16][LST]
+    int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);      // [16 regions][4 waves]
 
     const Geom &g = a.g;
-    const int ntiles = g.ntu * g.ntv;
-    const int tile = xcd_remap(blockIdx.x, ntiles);
-    if (tile < 0) return;
+    int4 item;                                                 // (tile, first, count, slot or -1)
+    if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
+    const int tile = item.x;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int qa = (wave >> 1) * 8, qb = (wave & 1) * 8;       // quadrant origin
-    const int la = qa + (lane >> 3), lb = qb + (lane & 7);     // this lane's cell
+    const int grp = lane >> 4, cell = lane & 15;
+    const int row = 4 * wave + (cell >> 2);                    // this lane's tile row
+    const int cc = cell & 3;                                   // column within a region
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
     // the four contributing bins as one concatenated list
@@ -93,138 +141,244 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, Cx<R> *__rest
         total += n;
         b_end[nb] = total;
     }
-    // the padding slot contributes nothing
+    // this item's share of the concatenated list
+    const uint32_t first = (uint32_t)item.y;
+    const uint32_t last = min(total, first + (uint32_t)item.z);
+    // the padding slot contributes nothing: zero value, zero kernel rows
     if (tid == 0) {
         s_d[CH] = cmake<C>((R)0, (R)0);
-        s_anc[CH] = make_int2(1 << 20, 1 << 20);
+        s_base[CH] = make_int2(CH * KP, CH * KP);
     }
-    if (tid < P) s_kw[CH * P + tid] = (R)0;
-    if (tid < ALPHA) {
-        s_ku[CH * ALPHA + tid] = (R)0;
-        s_kv[CH * ALPHA + tid] = (R)0;
+    if (tid < KP + 16) {
+        s_ku[CH * KP + tid] = (R)0;
+        s_kv[CH * KP + tid] = (R)0;
     }
-    R acc_re[P], acc_im[P];
+    if (tid < PS) s_kw[CH * PS + tid] = (R)0;
+    R acc_re[4][PS], acc_im[4][PS];
 #pragma unroll
-    for (int r = 0; r < P; ++r) acc_re[r] = acc_im[r] = (R)0;
-    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < PS; ++r) acc_re[q][r] = acc_im[q][r] = (R)0;
 
-    for (uint32_t base = 0; base < total; base += CH) {
+    for (uint32_t base = first; base < last; base += CH) {
         // ---- phase 1: one thread per visibility -------------------------
         const uint32_t pos = base + tid;
-        int qmask = 0;
-        if (pos < total) {
-            int nb = pos < b_end[0] ? 0 : pos < b_end[1] ? 1 : pos < b_end[2] ? 2 : 3;
-            const uint32_t s = b_s0[nb] + (pos - (nb ? b_end[nb - 1] : 0u));
+        int rmask = 0;
+        if (pos < last) {
+            // sorted position: select chain (no dynamic register indexing)
+            uint32_t s = b_s0[0] + pos;
+            s = pos >= b_end[0] ? b_s0[1] + (pos - b_end[0]) : s;
+            s = pos >= b_end[1] ? b_s0[2] + (pos - b_end[1]) : s;
+            s = pos >= b_end[2] ? b_s0[3] + (pos - b_end[2]) : s;
             const int2 an = a.anc[s];
             const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
             int la0 = iu - A * kTileCells;
             int lb0 = iv - B * kTileCells;
             if (la0 > g.nu / 2) la0 -= g.nu;
             if (lb0 > g.nv / 2) lb0 -= g.nv;
-            s_anc[tid] = make_int2(la0, lb0);
+            s_base[tid] = make_int2(tid * KP - la0 + 3, tid * KP - lb0 + 3);
+            int bm = 0, cm = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int oa = (q >> 1) * 8, ob = (q & 1) * 8;
-                if (la0 <= oa + 7 && la0 + ALPHA > oa && lb0 <= ob + 7 && lb0 + ALPHA > ob) qmask |= 1 << q;
+                if (la0 <= 4 * q + 3 && la0 + ALPHA > 4 * q) bm |= 1 << q;
+                if (lb0 <= 4 * q + 3 && lb0 + ALPHA > 4 * q) cm |= 1 << q;
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((bm >> q) & 1) rmask |= cm << (4 * q);
             s_d[tid] = a.vsorted[s];
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
             kernel_values_z<ALPHA, R>(zu, a.coef, a.degree, ku);
             kernel_values_z<ALPHA, R>(zv, a.coef, a.degree, kv);
+            R *pu = s_ku + tid * KP;
+            R *pv = s_kv + tid * KP;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                pu[i] = pv[i] = (R)0;
+                pu[ALPHA + 3 + i] = pv[ALPHA + 3 + i] = (R)0;
+            }
 #pragma unroll
             for (int i = 0; i < ALPHA; ++i) {
-                s_ku[tid * ALPHA + i] = ku[i];
-                s_kv[tid * ALPHA + i] = kv[i];
+                pu[3 + i] = ku[i];
+                pv[3 + i] = kv[i];
             }
-            // plane slot r holds plane j_lo + r; kernel index j - iw
+            // plane slot rr holds plane j_lo + rr; kernel index j - iw
             if (g.do_w) {
                 kernel_values_z<ALPHA, R>(zw, a.coef, a.degree, kw);
                 const int sh = j_lo - iw;                      // kernel index of slot 0
 #pragma unroll
-                for (int rr = 0; rr < P; ++rr) {
+                for (int rr = 0; rr < PS; ++rr) {
                     R wv = (R)0;
 #pragma unroll
                     for (int i = 0; i < ALPHA; ++i) wv = (i == rr + sh && j_lo + rr < j_hi) ? kw[i] : wv;
-                    s_kw[tid * P + rr] = wv;
+                    s_kw[tid * PS + rr] = wv;
                 }
             } else {
 #pragma unroll
-                for (int rr = 0; rr < P; ++rr) s_kw[tid * P + rr] = (R)(rr == 0);
+                for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = (R)(rr == 0);
             }
         }
-        // per-quadrant lists: wave-level ballots, then offsets across waves
-        unsigned long long bal[4];
+        // per-region lists: wave ballots, then offsets across waves
+        unsigned long long bal[ST::NREG];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            bal[q] = __ballot((qmask >> q) & 1);
-            if (lane == 0) s_cnt[q * 4 + wave] = (int)__popcll(bal[q]);
+        for (int rg = 0; rg < ST::NREG; ++rg) {
+            bal[rg] = __ballot((rmask >> rg) & 1);
+            if (lane == 0) s_cnt[rg * 4 + wave] = (int)__popcll(bal[rg]);
         }
         __syncthreads();
+        const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if ((qmask >> q) & 1) {
-                int off = 0;
-                for (int w = 0; w < wave; ++w) off += s_cnt[q * 4 + w];
-                s_list[q * CH + off + (int)__popcll(bal[q] & lt)] = (uint16_t)tid;
+        for (int rg = 0; rg < ST::NREG; ++rg) {
+            if ((rmask >> rg) & 1) {
+                const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
+                const int off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
+                s_list[rg * ST::LST + off + (int)__popcll(bal[rg] & lt)] = (uint16_t)tid;
             }
         }
+        // pad every list with the zero slot up to a multiple of 4, plus the
+        // 4 entries read ahead by the last step
+        if (tid < ST::NREG * 8) {
+            const int rg = tid >> 3, k = tid & 7;
+            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
+            const int n = c4.x + c4.y + c4.z + c4.w;
+            if (n + k < ((n + 3) & ~3) + 4) s_list[rg * ST::LST + n + k] = (uint16_t)CH;
+        }
         __syncthreads();
-        // ---- phase 2: this wave's quadrant, lanes = cells, 4 visibilities a step
-        const int n = s_cnt[wave * 4 + 0] + s_cnt[wave * 4 + 1] + s_cnt[wave * 4 + 2] + s_cnt[wave * 4 + 3];
-        const uint16_t *lst = s_list + wave * CH;
-        for (int j = 0; j < n; j += 4) {
-            int vv[4];
+        // ---- phase 2: this wave's four regions, four visibilities a step --
+        // (software-pipelined: the next step's list entry and row bases are
+        // read while the current step accumulates)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) vv[u] = (j + u < n) ? (int)lst[j + u] : CH;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int v = vv[u];
-                const int2 an = s_anc[v];
-                const int i = la - an.x, k = lb - an.y;
-                const bool act = (unsigned)i < (unsigned)ALPHA && (unsigned)k < (unsigned)ALPHA;
-                const int ic = act ? i : 0, kc = act ? k : 0;
-                const R wuv = act ? s_ku[v * ALPHA + ic] * s_kv[v * ALPHA + kc] : (R)0;
+        for (int q = 0; q < 4; ++q) {
+            const int rg = wave * 4 + q;
+            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
+            const int n4 = __builtin_amdgcn_readfirstlane((c4.x + c4.y + c4.z + c4.w + 3) & ~3);
+            const uint16_t *lst = s_list + rg * ST::LST + grp;
+            const int col = 4 * q + cc;
+            int v = lst[0];
+            int2 bs = s_base[v];
+            for (int j = 0; j < n4; j += 4) {
+                const R ku = s_ku[bs.x + row], kv = s_kv[bs.y + col];
                 const C d = s_d[v];
+                const R *kwp = s_kw + v * PS;
+                R kw[PS];
+#pragma unroll
+                for (int r = 0; r < PS; ++r) kw[r] = kwp[r];
+                int vn = lst[j + 4];
+                int2 bsn = s_base[vn];
+                const R wuv = ku * kv;
                 const R fr = d.x * wuv, fi = d.y * wuv;
 #pragma unroll
-                for (int r = 0; r < P; ++r) {
-                    const R kwv = s_kw[v * P + r];
-                    acc_re[r] += fr * kwv;
-                    acc_im[r] += fi * kwv;
+                for (int r = 0; r < PS; ++r) {
+                    acc_re[q][r] += fr * kw[r];
+                    acc_im[q][r] += fi * kw[r];
                 }
+                // keep the read-ahead values in registers (not re-read from
+                // LDS at the top of the next step)
+                asm volatile("" : "+v"(vn), "+v"(bsn.x), "+v"(bsn.y));
+                v = vn;
+                bs = bsn;
             }
         }
         __syncthreads();
     }
-    const int np = j_hi - j_lo;
-    const int64_t cell_off = (int64_t)(A * kTileCells + la) * g.nv + (B * kTileCells + lb);
+    // reduce-scatter over the four lane groups: group k ends with the total
+    // of region k (exchange halves across groups k^2, then k^1)
+    const bool hi2 = (grp & 2) != 0, hi1 = (grp & 1) != 0;
+    R tot_re[PS], tot_im[PS];
 #pragma unroll
-    for (int r = 0; r < P; ++r)
-        if (r < np) G[(int64_t)r * g.nu * g.nv + cell_off] = cmake<C>(acc_re[r], acc_im[r]);
+    for (int r = 0; r < PS; ++r) {
+        R y_re[2], y_im[2];
+#pragma unroll
+        for (int q0 = 0; q0 < 2; ++q0) {
+            const R keep_re = hi2 ? acc_re[q0 + 2][r] : acc_re[q0][r];
+            const R send_re = hi2 ? acc_re[q0][r] : acc_re[q0 + 2][r];
+            const R keep_im = hi2 ? acc_im[q0 + 2][r] : acc_im[q0][r];
+            const R send_im = hi2 ? acc_im[q0][r] : acc_im[q0 + 2][r];
+            y_re[q0] = keep_re + __shfl_xor(send_re, 32);
+            y_im[q0] = keep_im + __shfl_xor(send_im, 32);
+        }
+        const R keep_re = hi1 ? y_re[1] : y_re[0];
+        const R send_re = hi1 ? y_re[0] : y_re[1];
+        const R keep_im = hi1 ? y_im[1] : y_im[0];
+        const R send_im = hi1 ? y_im[0] : y_im[1];
+        tot_re[r] = keep_re + __shfl_xor(send_re, 16);
+        tot_im[r] = keep_im + __shfl_xor(send_im, 16);
+    }
+    // lane group k stores region k of the wave's band: 4 rows x 16 columns
+    const int np = j_hi - j_lo;
+    const int colw = 4 * grp + cc;
+    C *dst;
+    int64_t pstride;
+    if (item.w < 0) {
+        dst = G + (int64_t)(A * kTileCells + row) * g.nv + (B * kTileCells + colw);
+        pstride = (int64_t)g.nu * g.nv;
+    } else {
+        dst = part + (size_t)item.w * a.P * kTileArea + row * kTileCells + colw;
+        pstride = kTileArea;
+    }
+#pragma unroll
+    for (int r = 0; r < PS; ++r)
+        if (r < np) dst[r * pstride] = cmake<C>(tot_re[r], tot_im[r]);
+}
+
+// Adds the partial tiles of split gridder items to the grid planes, in item
+// order.  One workgroup per split tile (tile, first slot, slots), one thread
+// per cell.
+template <typename R>
+__global__ __launch_bounds__(256) void k_grid_reduce(const int4 *__restrict__ red, int n_red, int P, int np,
+                                                     Geom g, const Cx<R> *__restrict__ part,
+                                                     Cx<R> *__restrict__ G) {
+    using C = Cx<R>;
+    const int e = blockIdx.x;
+    if (e >= n_red) return;
+    const int4 r4 = red[e];
+    const int tile = r4.x;
+    const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
+    const int la = threadIdx.x >> 4, lb = threadIdx.x & 15;
+    const int64_t cell_off = (int64_t)(A * kTileCells + la) * g.nv + (B * kTileCells + lb);
+    for (int r = 0; r < np; ++r) {
+        C *gp = G + (int64_t)r * g.nu * g.nv + cell_off;
+        C acc = *gp;
+        for (int k = 0; k < r4.z; ++k) {
+            const C v = part[((size_t)(r4.y + k) * P + r) * kTileArea + threadIdx.x];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        *gp = acc;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Degridder (forward, bracket of eq. R3).  One workgroup per 16x16 tile and
-// batch: the tile plus its (alpha-1)-cell halo of the P planes is staged in
-// LDS, then each thread gathers alpha x alpha x (planes in batch) values for
-// its visibilities and adds the batch's partial sum to its accumulator.
+// Degridder (forward, bracket of eq. R3).  One workgroup per work item (a
+// run of at most a fixed number of the visibilities anchored in one 16x16
+// tile) and batch: the tile plus its (alpha-1)-cell halo of the P planes is
+// staged in LDS, then each thread gathers alpha x alpha x (planes in batch)
+// values for its visibilities and adds the batch's partial sum to its
+// accumulator.
 // ---------------------------------------------------------------------------
 template <typename R, int ALPHA>
-__global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, const Cx<R> *__restrict__ G,
+__global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, const int4 *__restrict__ extra,
+                                                int n_extra, int cap, const Cx<R> *__restrict__ G,
                                                 Cx<R> *__restrict__ visacc) {
     using C = Cx<R>;
     constexpr int W = kTileCells + ALPHA - 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *st = reinterpret_cast<C *>(smem_raw);                  // [PD][W][W]
     const Geom &g = a.g;
-    const int ntiles = g.ntu * g.ntv;
-    const int tile = xcd_remap(blockIdx.x, ntiles);
-    if (tile < 0) return;
+    int4 item;                                                 // (tile, first position, count, -)
+    if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
+    const int tile = item.x;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
-    const int64_t bin = tile;
-    const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
-    const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
+    uint32_t s0, s1;
+    if (item.w == -1) {                                        // first item of the tile: its bin's run
+        s0 = a.tab_lo[(int64_t)tile * (a.NJ + 1) + J];
+        const uint32_t e = a.tab_hi[(int64_t)tile * (a.NJ + 1) + J + 1];
+        s1 = e > s0 ? s0 + min(e - s0, (uint32_t)cap) : s0;
+    } else {
+        s0 = (uint32_t)item.y;
+        s1 = s0 + (uint32_t)item.z;
+    }
     if (s0 >= s1) return;
     const int tid = threadIdx.x;
     const int j_lo = J * a.P;

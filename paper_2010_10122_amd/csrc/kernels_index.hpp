@@ -201,6 +201,74 @@ __global__ void k_fill_tab(const unsigned long long *__restrict__ keys, int64_t 
     }
 }
 
+// ---- work items -------------------------------------------------------------
+// In batch J the gridder of tile t takes the visibilities of the four bins
+// whose footprints reach t (t and its neighbours up/left), the degridder
+// those of bin t alone.  A list longer than `cap` is dealt as ceil(len/cap)
+// items: the first is implied by the launch (one block per tile), the others
+// are listed here.  Run twice: emit = 0 counts the extra items per batch into
+// cur_*, emit = 1 (cursors cleared, off_* = per-batch list offsets) writes
+// them.  Gridder extras get consecutive partial-tile slots (numbered per
+// batch), recorded in `red` as (tile, first slot, slots) for the reduction;
+// the list order depends on the atomics, the slot order within a tile does
+// not.
+__device__ __forceinline__ uint32_t bin_len(const uint32_t *__restrict__ tab_lo, const uint32_t *__restrict__ tab_hi,
+                                            int64_t bin, int NJ, int J) {
+    const uint32_t s0 = tab_lo[bin * (NJ + 1) + J];
+    const uint32_t s1 = tab_hi[bin * (NJ + 1) + J + 1];
+    return s1 > s0 ? s1 - s0 : 0u;
+}
+
+__global__ void k_items(const uint32_t *__restrict__ tab_lo, const uint32_t *__restrict__ tab_hi, int ntu,
+                        int ntv, int NJ, uint32_t cap_g, uint32_t cap_d, int emit, uint32_t *__restrict__ cur_g,
+                        uint32_t *__restrict__ cur_d, uint32_t *__restrict__ cur_r,
+                        const uint32_t *__restrict__ off_g, const uint32_t *__restrict__ off_d,
+                        const uint32_t *__restrict__ off_r, int4 *__restrict__ items_g,
+                        int4 *__restrict__ items_d, int4 *__restrict__ red) {
+    const int64_t nt = (int64_t)ntu * ntv;
+    const int64_t n = nt * NJ;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int J = (int)(e / nt);
+        const int t = (int)(e - (int64_t)J * nt);
+        const int A = t / ntv, B = t - (t / ntv) * ntv;
+        uint32_t cg = 0;
+        for (int nb = 0; nb < 4; ++nb) {
+            int tu = A - 1 + (nb >> 1), tv = B - 1 + (nb & 1);
+            if (tu < 0) tu += ntu;
+            if (tv < 0) tv += ntv;
+            cg += bin_len(tab_lo, tab_hi, (int64_t)tu * ntv + tv, NJ, J);
+        }
+        const uint32_t cd = bin_len(tab_lo, tab_hi, t, NJ, J);
+        const uint32_t eg = cg > cap_g ? (cg - 1) / cap_g : 0u;
+        const uint32_t ed = cd > cap_d ? (cd - 1) / cap_d : 0u;
+        if (!emit) {
+            if (eg) {
+                atomicAdd(&cur_g[J], eg);
+                atomicAdd(&cur_r[J], 1u);
+            }
+            if (ed) atomicAdd(&cur_d[J], ed);
+            continue;
+        }
+        if (eg) {
+            const uint32_t b = atomicAdd(&cur_g[J], eg);
+            for (uint32_t k = 1; k <= eg; ++k) {
+                const uint32_t first = k * cap_g;
+                items_g[off_g[J] + b + k - 1] = make_int4(t, (int)first, (int)min(cap_g, cg - first), (int)(b + k - 1));
+            }
+            const uint32_t r = atomicAdd(&cur_r[J], 1u);
+            red[off_r[J] + r] = make_int4(t, (int)b, (int)eg, 0);
+        }
+        if (ed) {
+            const uint32_t s0 = tab_lo[(int64_t)t * (NJ + 1) + J];
+            const uint32_t b = atomicAdd(&cur_d[J], ed);
+            for (uint32_t k = 1; k <= ed; ++k) {
+                const uint32_t first = k * cap_d;
+                items_d[off_d[J] + b + k - 1] = make_int4(t, (int)(s0 + first), (int)min(cap_d, cd - first), 0);
+            }
+        }
+    }
+}
+
 // ---- per sorted visibility: kernel-local coordinates and anchors ------------
 // z = 2 (first cell - coordinate + alpha/2) - 1 in [-1, 1) for u, v and w
 // (the shared local variable of the alpha polynomial pieces), anchors packed

@@ -216,10 +216,15 @@ struct wg_plan {
     uint32_t *tab_lo = nullptr, *tab_hi = nullptr;
     void *zc = nullptr;                // [n_active][3] R: kernel-local coordinates
     int2 *anc = nullptr;               // [n_active] anchors and fold bit
+    // extra work items per batch (lists longer than the item cap); offsets into
+    // the device lists, [NJ + 1] each
+    std::vector<uint32_t> xg_off, xd_off, xr_off;
+    int4 *xg = nullptr, *xd = nullptr, *xr = nullptr;
+    int max_slots = 0;                 // partial tiles of the gridder in one batch
     size_t index_bytes = 0;
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
-    size_t off_G = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0;
+    size_t off_G = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
 };
 
 namespace {
@@ -310,6 +315,61 @@ int radix_sort(wg_plan *p, unsigned long long *const keys_io, uint32_t *const va
     p->mem.put(hist);
     for (uint32_t *b : levels) p->mem.put(b);
     return rc;
+}
+
+// Extra work items of every batch (see k_items): count, lay out per batch,
+// emit.  Leaves xg/xd/xr and their per-batch offsets in the plan.
+int build_items(wg_plan *p, hipStream_t st) {
+    const int NJ = p->NJ;
+    const int64_t n = (int64_t)p->g.ntu * p->g.ntv * NJ;
+    uint32_t *cur = (uint32_t *)p->mem.get((size_t)6 * NJ * sizeof(uint32_t));
+    if (!cur) return WG_ENOMEM;
+    uint32_t *cur_g = cur, *cur_d = cur + NJ, *cur_r = cur + 2 * NJ;
+    uint32_t *doff = cur + 3 * NJ;
+    const unsigned nb = (unsigned)grid_blocks(n, 256, 1 << 16);
+    hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3((unsigned)grid_blocks(6 * NJ, 256, 1024)), dim3(256), 0, st, cur,
+                       (int64_t)6 * NJ);
+    hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
+                       (uint32_t)kGridItemCap, (uint32_t)kDegridItemCap, 0, cur_g, cur_d, cur_r, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr);
+    std::vector<uint32_t> cnt((size_t)3 * NJ);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), cur, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->xg_off.assign(NJ + 1, 0);
+    p->xd_off.assign(NJ + 1, 0);
+    p->xr_off.assign(NJ + 1, 0);
+    p->max_slots = 0;
+    for (int J = 0; J < NJ; ++J) {
+        p->xg_off[J + 1] = p->xg_off[J] + cnt[J];
+        p->xd_off[J + 1] = p->xd_off[J] + cnt[NJ + J];
+        p->xr_off[J + 1] = p->xr_off[J] + cnt[2 * NJ + J];
+        p->max_slots = std::max(p->max_slots, (int)cnt[J]);
+    }
+    const uint32_t ng = p->xg_off[NJ], nd = p->xd_off[NJ], nr = p->xr_off[NJ];
+    p->xg = (int4 *)p->mem.get(std::max<size_t>(ng, 1) * sizeof(int4));
+    p->xd = (int4 *)p->mem.get(std::max<size_t>(nd, 1) * sizeof(int4));
+    p->xr = (int4 *)p->mem.get(std::max<size_t>(nr, 1) * sizeof(int4));
+    if (!p->xg || !p->xd || !p->xr) return WG_ENOMEM;
+    if (ng + nd > 0) {
+        std::vector<uint32_t> offs((size_t)3 * NJ);
+        for (int J = 0; J < NJ; ++J) {
+            offs[J] = p->xg_off[J];
+            offs[NJ + J] = p->xd_off[J];
+            offs[2 * NJ + J] = p->xr_off[J];
+        }
+        HIP_TRY(hipMemcpyAsync(doff, offs.data(), offs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3((unsigned)grid_blocks(3 * NJ, 256, 1024)), dim3(256), 0, st,
+                           cur, (int64_t)3 * NJ);
+        hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
+                           (uint32_t)kGridItemCap, (uint32_t)kDegridItemCap, 1, cur_g, cur_d, cur_r, doff,
+                           doff + NJ, doff + 2 * NJ, p->xg, p->xd, p->xr);
+        if (!hip_ok(hipGetLastError(), "k_items")) return WG_EHIP;
+        HIP_TRY(hipStreamSynchronize(st));   // the host offsets buffer must outlive the copy
+    }
+    p->mem.put(cur);
+    p->index_bytes += (size_t)(std::max<uint32_t>(ng, 1) + std::max<uint32_t>(nd, 1) + std::max<uint32_t>(nr, 1)) *
+                      sizeof(int4);
+    return WG_OK;
 }
 
 int validate(const wg_plan_desc *d) {
@@ -427,8 +487,11 @@ int plan_build(wg_plan *p) {
     // planes per batch: the gridder keeps one register accumulator per plane
     // of the batch and lane, P = alpha (a visibility's alpha planes then meet
     // at most two batches); the degridder stages P planes of tile + halo.
+    // planes per batch: at most alpha, and at most the gridder's register
+    // plane slots (8 in FP32, 4 in FP64)
+    const int max_slots = d.precision == WG_F32 ? 8 : 4;
     p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, p->alpha) : p->alpha;
-    p->P = std::min(p->P, g.nw);
+    p->P = std::min(std::min(p->P, max_slots), g.nw);
     (void)sc;
     p->NJ = (g.nw + p->P - 1) / p->P;
     make_fft_desc(g.nu, p->fft_u);
@@ -496,6 +559,11 @@ int plan_build(wg_plan *p) {
     hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
                        p->keys, p->n_active, g.nw, p->P, p->NJ, 0, tab_n, p->tab_hi);
     LAUNCH_CHECK("k_fill_tab");
+    // work items: lists of the gridder and degridder beyond the item cap
+    {
+        rc = build_items(p, st);
+        if (rc != WG_OK) return rc;
+    }
     // sorted per-visibility stream: kernel-local coordinates and anchors
     const int64_t nact = std::max<int64_t>(p->n_active, 1);
     p->zc = p->mem.get(nact * 3 * sr);
@@ -510,8 +578,8 @@ int plan_build(wg_plan *p) {
                                0, st, d.uvw, p->scale, p->order, p->n_active, g, (double *)p->zc, p->anc);
         LAUNCH_CHECK("k_vis_prep");
     }
-    p->index_bytes = nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t) +
-                     nact * (3 * sr + sizeof(int2));
+    p->index_bytes += nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t) +
+                      nact * (3 * sr + sizeof(int2));
     HIP_TRY(hipStreamSynchronize(st));
     p->mem.put(dpx);
     p->mem.put(dpy);
@@ -531,37 +599,64 @@ int plan_build(wg_plan *p) {
     off = align(off + (size_t)npix * sr);
     p->off_vacc = off;
     off = align(off + (size_t)std::max<int64_t>(p->n_active, 1) * sc);
+    p->off_part = off;
+    off = align(off + (size_t)p->max_slots * p->P * kTile * kTile * sc);
     p->ws_bytes = off;
     return WG_OK;
 }
 
 // ---- apply ------------------------------------------------------------------
 
+// blocks of a vis-kernel launch: the extra items (padded to a multiple of
+// 8) and then one block per tile (padded likewise)
+inline unsigned item_blocks(const wg_plan *p, uint32_t n_extra) {
+    const int nt = p->g.ntu * p->g.ntv;
+    return (unsigned)(((n_extra + 7) & ~7u) + (((unsigned)nt + 7) & ~7u));
+}
+
 template <typename R, int ALPHA> struct Launch {
-    static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, hipStream_t st) {
-        const int nt = p->g.ntu * p->g.ntv;
-        const int nb = ((nt + 7) / 8) * 8;
-        const size_t lds = GridStage<R, ALPHA>::bytes;
-        hipLaunchKernelGGL((k_grid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, G);
+    template <int PS>
+    static void grid_ps(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
+        const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
+        const size_t lds = GridStage<R, ALPHA, PS>::bytes;
+        hipLaunchKernelGGL((k_grid<R, ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
+                           p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
+    }
+    static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
+        bool done = false;
+        if constexpr (sizeof(R) == 4) {
+            if (p->P > 4) {
+                grid_ps<8>(p, va, J, G, part, st);
+                done = true;
+            }
+        }
+        if (!done) grid_ps<4>(p, va, J, G, part, st);
+        // partial tiles of split items, added in item order
+        const uint32_t nr = p->xr_off[J + 1] - p->xr_off[J];
+        if (nr > 0) {
+            const int np = std::min(p->P, p->g.nw - J * p->P);
+            hipLaunchKernelGGL(k_grid_reduce<R>, dim3(nr), dim3(kTileArea), 0, st, p->xr + p->xr_off[J], (int)nr,
+                               p->P, np, p->g, (const Cx<R> *)part, G);
+        }
     }
     static void degrid(const wg_plan *p, const VisArgs<R> &va, int J, const Cx<R> *G, Cx<R> *vacc,
                        hipStream_t st) {
-        const int nt = p->g.ntu * p->g.ntv;
-        const int nb = ((nt + 7) / 8) * 8;
+        const uint32_t ne = p->xd_off[J + 1] - p->xd_off[J];
         const int W = kTileCells + ALPHA - 1;
         const int pd = std::max(1, std::min(p->P, (int)(72 * 1024 / ((size_t)W * W * sizeof(Cx<R>)))));
         const size_t lds = (size_t)pd * W * W * sizeof(Cx<R>);
-        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(nb), dim3(256), lds, st, va, J, pd, G, vacc);
+        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J, pd,
+                           p->xd + p->xd_off[J], (int)ne, kDegridItemCap, G, vacc);
     }
 };
 
 template <typename R>
 void launch_vis_kernel(bool gridding, const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *vacc,
-                       hipStream_t st) {
+                       Cx<R> *part, hipStream_t st) {
     switch (p->alpha) {
 #define CASE(A)                                                              \
     case A:                                                                  \
-        if (gridding) Launch<R, A>::grid(p, va, J, G, st);                   \
+        if (gridding) Launch<R, A>::grid(p, va, J, G, part, st);             \
         else Launch<R, A>::degrid(p, va, J, G, vacc, st);                    \
         break;
         CASE(4) CASE(7) CASE(8) CASE(12) CASE(16)
@@ -633,6 +728,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     R *acc = (R *)(w + p->off_acc);
     R *itil = (R *)(w + p->off_itil);
     C *vacc = (C *)(w + p->off_vacc);
+    C *part = (C *)(w + p->off_part);
     const int64_t npix = (int64_t)g.npix_x * g.npix_y;
 
     VisArgs<R> va;
@@ -665,7 +761,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 const int np = std::min(p->P, g.nw - j_lo);
                 {
                     ProfScope ps(WG_KIND_GRID, st);
-                    launch_vis_kernel<R>(true, p, va, J, G, nullptr, st);
+                    launch_vis_kernel<R>(true, p, va, J, G, nullptr, part, st);
                 }
                 {
                     ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
@@ -712,7 +808,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 }
                 {
                     ProfScope ps(WG_KIND_DEGRID, st);
-                    launch_vis_kernel<R>(false, p, va, J, G, vacc, st);
+                    launch_vis_kernel<R>(false, p, va, J, G, vacc, nullptr, st);
                 }
             }
             {
@@ -828,6 +924,8 @@ int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
     info->plan_bytes = p->mem.total;
     info->index_bytes = p->index_bytes;
     info->workspace_bytes = p->ws_bytes;
+    info->extra_items_grid = p->xg_off.empty() ? 0 : p->xg_off.back();
+    info->extra_items_degrid = p->xd_off.empty() ? 0 : p->xd_off.back();
     return WG_OK;
 }
 
