@@ -54,6 +54,28 @@ def kernel_bytes(info, kind, n_launch_planes, precision):
     return float("nan")
 
 
+def profiled_traffic(kind):
+    """HBM bytes per dispatch of ``kind`` from the committed rocprofv3 counter
+    summary of this workload (2 x FETCH_SIZE + WRITE_SIZE, see the profile
+    file), or None when the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wide_field_f32_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    src = sorted(glob.glob(os.path.join(ROOT, "paper_2010_10122_amd", "csrc", "*")))
+    h = hashlib.sha1(b"".join(open(q, "rb").read() for q in src)).hexdigest()
+    if vals.get("source_sha1") != h or kind not in vals:
+        return None
+    return float(vals[kind])
+
+
 def cpu_baseline(case, budget_terms=6e8):
     """Oracle O1 (direct DFT, FP64, OpenMP C) on a bounded sample of the
     workload: degrid a sample of visibilities against the point-source image
@@ -324,8 +346,9 @@ def main():
     planes_per_launch = info["nw"] / math.ceil(info["nw"] / info["planes_per_batch"])
     bytes_launch = kernel_bytes(info, dom, planes_per_launch, "f32")
     achieved = bytes_launch / avg_s / 1e9
+    traffic = profiled_traffic(dom) if args.dumps == 2880 else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": round(avg_s * 1e3, 4), "bytes_per_launch": bytes_launch, "launches": nl}
     per_kernel = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                       "avg_ms": round(v[0] / v[1], 4) if v[1] else None,
