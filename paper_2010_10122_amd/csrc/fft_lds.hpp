@@ -1,21 +1,99 @@
-// Mixed-radix FFT of K interleaved columns held in LDS (gfx950).
+// Mixed-radix FFT of K interleaved columns (gfx950).
 //
 // Stockham autosort formulation: pass s with radix R reads butterfly j from
 // j + r*N/R, applies the twiddles exp(dir 2 pi i (j mod Ns) r / (Ns R)),
-// does a radix-R DFT and writes to (j div Ns) Ns R + (j mod Ns) + r Ns; after
-// all passes the data are in natural order.  There is one LDS buffer: every
-// thread first pulls all of its butterfly inputs into registers, the
-// workgroup synchronises, then the outputs are written back.  Element n of
-// column k lives at buf[n * K + k], so K contiguous global values map to K
-// contiguous LDS words.  Twiddles come from a per-length table
+// does a radix-R DFT in registers and writes to
+// (j div Ns) Ns R + (j mod Ns) + r Ns; after all passes the data are in
+// natural order.  Radices go up to 16 (composite ones as two register
+// stages with compile-time inner twiddles), so a length of a few thousand
+// takes three passes.  The first pass reads its inputs straight from the
+// caller (global memory, with any fused pre-processing) and the last pass
+// hands its outputs straight to the caller, so only the passes in between
+// go through LDS.  There is one LDS buffer: every thread pulls all of its
+// butterfly inputs into registers, the workgroup synchronises, then the
+// outputs are written back.  Element n of column k lives at
+// buf[(n + n/16) * K + k] (one pad element per 16 against bank conflicts of
+// the strided writes), so K contiguous global values map to K contiguous LDS
+// words.  Inter-pass twiddles come from a per-length table
 // tw[t] = exp(-2 pi i t / N) computed in FP64 on the host.
 #pragma once
+#include <utility>
 #include "device_common.hpp"
 
 namespace wg {
 
 constexpr int kFftMaxPass = 16;
-constexpr int kFftMaxC = 24;      // complex values a thread holds per pass
+constexpr int kFftMaxC = 24;      // complex values a thread holds per pass (N * K <= threads * kFftMaxC)
+constexpr int kFftMaxSlots = 32;  // last-pass outputs per thread: ceil(kFftMaxC / R) * R <= 32 for R <= 16
+
+// LDS words for length n (pad included)
+__host__ __device__ constexpr int fft_lds_len(int n) { return n + n / 16; }
+__device__ __forceinline__ int fft_lidx(int o) { return o + (o >> 4); }
+
+// ---- compile-time roots of unity ------------------------------------------
+// sin and cos of small arguments by their Taylor series; 2 pi m / r is first
+// reduced exactly (in integers) to an angle in [0, pi/4] and an octant.
+constexpr double ct_sin_small(double x) {
+    double term = x, sum = x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ct_cos_small(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+// cos or sin (want_sin) of 2 pi m / r
+constexpr double ct_trig2pi(long m, long r, bool want_sin) {
+    m %= r;
+    if (m < 0) m += r;
+    // angle = 2 pi m / r = (pi/4) * (8 m / r): octant q and remainder f = (8m mod r) / r in [0, 1)
+    const long q = (8 * m) / r;
+    const long rem = 8 * m - q * r;
+    const double pi4 = 0.78539816339744830961566084581988;
+    double t = pi4 * (double)rem / (double)r;          // in [0, pi/4)
+    // odd octants: use pi/4 - t about the octant boundary
+    const bool odd = (q & 1) != 0;
+    if (odd) t = pi4 * (double)(r - rem) / (double)r;
+    const double s0 = ct_sin_small(t), c0 = ct_cos_small(t);
+    // base angle of the octant pair: q / 2 quarter turns; within it, angle = t (even) or pi/2 - t (odd)
+    double c = odd ? s0 : c0, s = odd ? c0 : s0;       // cos, sin of the angle within the quarter
+    const long quarter = q / 2;
+    double cr = c, sr = s;
+    if (quarter == 1) { cr = -s; sr = c; }
+    else if (quarter == 2) { cr = -c; sr = -s; }
+    else if (quarter == 3) { cr = s; sr = -c; }
+    return want_sin ? sr : cr;
+}
+
+template <int R, int M, int DIR> struct Root {
+    static constexpr double re = ct_trig2pi(M, R, false);
+    static constexpr double im = DIR * ct_trig2pi(M, R, true);
+};
+
+// v * exp(DIR 2 pi i M / R)
+template <int R, int M, int DIR, typename C> __device__ __forceinline__ C rot(C v) {
+    using T = decltype(C{}.x);
+    constexpr int m = M % R;
+    if constexpr (m == 0) {
+        return v;
+    } else if constexpr (4 * m == R) {
+        return cmul_i<DIR>(v);
+    } else if constexpr (2 * m == R) {
+        return cmake<C>(-v.x, -v.y);
+    } else if constexpr (4 * m == 3 * R) {
+        return cmul_i<-DIR>(v);
+    } else {
+        constexpr T c = (T)Root<R, M, DIR>::re, s = (T)Root<R, M, DIR>::im;
+        return cmake<C>(v.x * c - v.y * s, v.x * s + v.y * c);
+    }
+}
 
 struct FftDesc {
     int n;                        // transform length
@@ -142,65 +220,184 @@ template <int DIR, typename C> struct Dft<8, DIR, C> {
     }
 };
 
-template <int RADIX, int DIR, typename C>
-__device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw,
-                                         int tid, int nth) {
+
+// Composite radix A*B in registers: A-point DFTs over x[B n1 + n2] for each
+// n2, inner twiddles exp(DIR 2 pi i n2 k1 / (A B)), then B-point DFTs over
+// n2 for each k1; output k1 + A k2.
+template <int A, int B, int DIR, typename C> struct DftComp {
+    static constexpr int R = A * B;
+    template <int... I> __device__ __forceinline__ static void twid(C *y, std::integer_sequence<int, I...>) {
+        ((y[I] = rot<R, (I / A) * (I % A), DIR, C>(y[I])), ...);
+    }
+    __device__ __forceinline__ static void run(C *v) {
+        C y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) {
+            C t[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
+            Dft<A, DIR, C>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) y[n2 * A + k1] = t[k1];
+        }
+        twid(y, std::make_integer_sequence<int, R>{});
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            C t[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) t[n2] = y[n2 * A + k1];
+            Dft<B, DIR, C>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = t[k2];
+        }
+    }
+};
+template <int DIR, typename C> struct Dft<6, DIR, C> : DftComp<2, 3, DIR, C> {};
+template <int DIR, typename C> struct Dft<9, DIR, C> : DftComp<3, 3, DIR, C> {};
+template <int DIR, typename C> struct Dft<10, DIR, C> : DftComp<2, 5, DIR, C> {};
+template <int DIR, typename C> struct Dft<12, DIR, C> : DftComp<4, 3, DIR, C> {};
+template <int DIR, typename C> struct Dft<14, DIR, C> : DftComp<2, 7, DIR, C> {};
+template <int DIR, typename C> struct Dft<15, DIR, C> : DftComp<3, 5, DIR, C> {};
+template <int DIR, typename C> struct Dft<16, DIR, C> : DftComp<4, 4, DIR, C> {};
+
+// One Stockham pass of radix RADIX over K interleaved columns of length N.
+// first: inputs come from load(n, col) instead of LDS; last: outputs go to
+// store(o, col, value, slot) instead of LDS, slot = b * RADIX + r being fixed
+// for a given (thread, output) so that callers may keep per-output
+// registers.  Barriers: a pass that reads and then writes LDS synchronises
+// in between; a pass that writes LDS synchronises after.
+template <int RADIX, int DIR, int NTH, bool first, bool last, typename C, typename Load, typename Store>
+__device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
+                                         Store &store) {
     constexpr int MAXB = (kFftMaxC + RADIX - 1) / RADIX;
+    const int tid = threadIdx.x;
     const int M = N / RADIX;
     const int W = M * K;
     const int tstride = N / (Ns * RADIX);
     C v[MAXB][RADIX];
+    if constexpr (first) {
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b) {
-        int w = tid + b * nth;
-        if (w < W) {
-            int j = w / K, col = w - j * K;
+        for (int b = 0; b < MAXB; ++b) {
+            const int w = tid + b * NTH;
+            if (w < W) {
+                const int j = w / K, col = w - j * K;
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[b][r] = buf[(j + r * M) * K + col];
+                for (int r = 0; r < RADIX; ++r) v[b][r] = load(j + r * M, col);
+            }
         }
+    } else {
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) {
+            const int w = tid + b * NTH;
+            if (w < W) {
+                const int j = w / K, col = w - j * K;
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) v[b][r] = buf[fft_lidx(j + r * M) * K + col];
+            }
+        }
+        if constexpr (!last) __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-        int w = tid + b * nth;
+        const int w = tid + b * NTH;
         if (w < W) {
-            int j = w / K, col = w - j * K;
-            int jm = j % Ns;
+            const int j = w / K, col = w - j * K;
+            const int jm = j % Ns;
             if (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
-                    C t = tw[jm * r * tstride];
+                    const C t = tw[jm * r * tstride];
                     v[b][r] = DIR < 0 ? cmul(v[b][r], t) : cmulconj(v[b][r], t);
                 }
             }
             Dft<RADIX, DIR, C>::run(v[b]);
-            int base = (j - jm) * RADIX + jm;
+            const int base = (j - jm) * RADIX + jm;
+            if constexpr (last) {
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[(base + r * Ns) * K + col] = v[b][r];
+                for (int r = 0; r < RADIX; ++r) store(base + r * Ns, col, v[b][r], b * RADIX + r);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) buf[fft_lidx(base + r * Ns) * K + col] = v[b][r];
+            }
         }
     }
-    __syncthreads();
+    if constexpr (!last) __syncthreads();
 }
 
-// In-place (in LDS) FFT of K interleaved columns of length d.n.  Requires
-// d.n * K <= nth * kFftMaxC.  Caller synchronises before (data loaded) and
-// may read the result after return (ends with a barrier).
-template <int DIR, typename C>
-__device__ void lds_fft(C *buf, int K, const FftDesc &d, const C *__restrict__ tw, int tid, int nth) {
-    int Ns = 1;
-    for (int s = 0; s < d.npass; ++s) {
-        const int r = d.radix[s];
+// a middle pass (LDS to LDS) as a function of its own: keeps the register
+// allocation of the passes separate
+struct NoIo {
+    template <typename... A> __device__ __forceinline__ void operator()(A...) const {}
+};
+template <int RADIX, int DIR, int NTH, typename C>
+__device__ __noinline__ void fft_pass_mid(C *buf, int N, int K, int Ns, const C *__restrict__ tw) {
+    NoIo none;
+    fft_pass<RADIX, DIR, NTH, false, false>(buf, N, K, Ns, tw, none, none);
+}
+
+// one pass of runtime radix r with compile-time role
+template <int DIR, int NTH, bool first, bool last, typename C, typename Load, typename Store>
+__device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, const C *__restrict__ tw,
+                                           Load &load, Store &store) {
+    if constexpr (!first && !last) {
         switch (r) {
-            case 8: fft_pass<8, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
-            case 4: fft_pass<4, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
-            case 2: fft_pass<2, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
-            case 3: fft_pass<3, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
-            case 5: fft_pass<5, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
-            case 7: fft_pass<7, DIR>(buf, d.n, K, Ns, tw, tid, nth); break;
+            case 16: fft_pass_mid<16, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 15: fft_pass_mid<15, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 14: fft_pass_mid<14, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 12: fft_pass_mid<12, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 10: fft_pass_mid<10, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 9: fft_pass_mid<9, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 8: fft_pass_mid<8, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 7: fft_pass_mid<7, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 6: fft_pass_mid<6, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 5: fft_pass_mid<5, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 4: fft_pass_mid<4, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 3: fft_pass_mid<3, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 2: fft_pass_mid<2, DIR, NTH>(buf, N, K, Ns, tw); break;
             default: break;
         }
-        Ns *= r;
+        return;
     }
+    switch (r) {
+        case 16: fft_pass<16, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 15: fft_pass<15, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 14: fft_pass<14, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 12: fft_pass<12, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 10: fft_pass<10, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 9: fft_pass<9, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 8: fft_pass<8, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 7: fft_pass<7, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 6: fft_pass<6, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 5: fft_pass<5, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 4: fft_pass<4, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 3: fft_pass<3, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 2: fft_pass<2, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        default: break;
+    }
+}
+
+// FFT of K interleaved columns of length d.n (d.n * K <= NTH * kFftMaxC).
+// Input: with IN_LDS the caller has written element n of column col to
+// buf[fft_lidx(n) * K + col] and synchronised; otherwise the first pass
+// calls load(n, col) -> C.  Output: with OUT_LDS the result is left at
+// buf[fft_lidx(o) * K + col] (synchronised); otherwise the last pass calls
+// store(o, col, value, slot).  buf holds fft_lds_len(d.n) * K complex
+// values.  The caller must synchronise between two calls that share buf.
+// Passes that only move data between LDS buffers run as functions of their
+// own (fft_pass_mid), which keeps each pass's register allocation apart.
+template <bool IN_LDS, bool OUT_LDS, int DIR, int NTH, typename C, typename Load, typename Store>
+__device__ __forceinline__ void lds_fft(C *buf, int K, const FftDesc &d, const C *__restrict__ tw, Load &&load,
+                                        Store &&store) {
+    // d.npass >= 2: every length here is a multiple of 16 and at least 48
+    if constexpr (IN_LDS) fft_pass_r<DIR, NTH, false, false>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    else fft_pass_r<DIR, NTH, true, false>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    int Ns = d.radix[0];
+    for (int s = 1; s < d.npass - 1; ++s) {
+        fft_pass_r<DIR, NTH, false, false>(d.radix[s], buf, d.n, K, Ns, tw, load, store);
+        Ns *= d.radix[s];
+    }
+    if constexpr (OUT_LDS) fft_pass_r<DIR, NTH, false, false>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
+    else fft_pass_r<DIR, NTH, false, true>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
 }
 
 }  // namespace wg

@@ -457,6 +457,7 @@ struct PassGeom {
 
 // Gridding pass 1: row a of plane p: T[p][a][q] = sum_b G[p][a][b] e^{+2 pi i b q'/N_v}
 // for the npix_y retained q (q' = q - npix_y/2), i.e. the pruned output.
+// The first FFT pass reads the row from HBM, the last writes T.
 template <typename R, int NTH>
 __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, Cx<R> *__restrict__ T,
                                                    PassGeom pg, FftDesc fd, const Cx<R> *__restrict__ tw) {
@@ -465,22 +466,23 @@ __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, 
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int a = blockIdx.x, p = blockIdx.y;
     const C *src = G + ((int64_t)p * pg.nu + a) * pg.nv;
-    for (int e = threadIdx.x; e < pg.nv; e += NTH) buf[e] = src[e];
-    __syncthreads();
-    lds_fft<+1>(buf, 1, fd, tw, threadIdx.x, NTH);
     C *dst = T + ((int64_t)p * pg.nu + a) * pg.npix_y;
     const int h = pg.npix_y / 2;
-    for (int q = threadIdx.x; q < pg.npix_y; q += NTH) {
-        int b = q - h;
-        if (b < 0) b += pg.nv;
-        dst[q] = buf[b];
-    }
+    lds_fft<false, false, +1, NTH>(
+        buf, 1, fd, tw, [&](int n, int) { return src[n]; },
+        [&](int o, int, C v, int) {
+            // output frequency o holds image column q with o = (q - h) mod N_v
+            int q = o + h;
+            if (q >= pg.nv) q -= pg.nv;
+            if (q < pg.npix_y) dst[q] = v;
+        });
 }
 
 // Gridding pass 2: K columns q of every plane in the batch, transform along
 // u, keep the npix_x retained p, multiply by the conjugate w-screen
 // exp(-2 pi i c_j (n - 1)) (eq. Rad1, phase reduced in FP64) and add the
-// real part into the image accumulator (owned by this workgroup).
+// real part into the image accumulator (owned by this workgroup).  The sum
+// over the batch's planes stays in LDS and is added to the image once.
 template <typename R, int NTH>
 __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, R *__restrict__ acc,
                                                    const double *__restrict__ nm1, PassGeom pg, int K,
@@ -495,24 +497,34 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     const int q0 = cb * K;
     const int kk = min(K, pg.npix_y - q0);
     const int h = pg.npix_x / 2;
+    // the image pixels of this column block, summed over the batch's planes
+    // in LDS behind the FFT buffer (each thread owns pixels e = tid + i * NTH)
+    // and added to the image once
+    R *sum = reinterpret_cast<R *>(buf + (size_t)fft_lds_len(pg.nu) * K);
+    const int ne = pg.npix_x * kk;
+    for (int e = threadIdx.x; e < ne; e += NTH) sum[e] = (R)0;
     for (int p = 0; p < np; ++p) {
         const C *src = T + (int64_t)p * pg.nu * pg.npix_y;
-        for (int e = threadIdx.x; e < pg.nu * K; e += NTH) {
-            const int a = e / K, col = e - a * K;
-            buf[e] = col < kk ? src[(int64_t)a * pg.npix_y + q0 + col] : cmake<C>((R)0, (R)0);
-        }
-        __syncthreads();
-        lds_fft<+1>(buf, K, fd, tw, threadIdx.x, NTH);
         const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
-        for (int e = threadIdx.x; e < pg.npix_x * kk; e += NTH) {
+        // an opaque copy of K per plane: otherwise every FFT address is
+        // hoisted out of the plane loop and held in registers across it
+        int Kp = __builtin_amdgcn_readfirstlane(K);
+        asm volatile("" : "+s"(Kp));
+        lds_fft<false, true, +1, NTH>(
+            buf, Kp, fd, tw,
+            [&](int n, int col) {
+                return col < kk ? src[(int64_t)n * pg.npix_y + q0 + col] : cmake<C>((R)0, (R)0);
+            },
+            NoIo{});
+        for (int e = threadIdx.x; e < ne; e += NTH) {
             const int pp = e / kk, col = e - pp * kk;
+            // image row pp sits at grid row (pp - h) mod N_u
             int ga = pp - h;
             if (ga < 0) ga += pg.nu;
-            const C hv = buf[ga * K + col];
-            const int64_t pix = (int64_t)pp * pg.npix_y + q0 + col;
+            const C hv = buf[fft_lidx(ga) * K + col];
             R val;
             if (pg.do_w) {
-                double ph = cj * nm1[pix];
+                double ph = cj * nm1[(int64_t)pp * pg.npix_y + q0 + col];
                 ph -= rint(ph);
                 R sn, cs;
                 if constexpr (sizeof(R) == 4) sincospif((float)(2.0 * ph), &sn, &cs);
@@ -521,16 +533,20 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
             } else {
                 val = hv.x;
             }
-            acc[pix] += val;
+            sum[e] += val;
         }
         __syncthreads();
+    }
+    for (int e = threadIdx.x; e < ne; e += NTH) {
+        const int pp = e / kk, col = e - pp * kk;
+        acc[(int64_t)pp * pg.npix_y + q0 + col] += sum[e];
     }
 }
 
 // Degridding pass A: image row p, for every plane of the batch: screened
 // row I~ exp(+2 pi i c_j (n - 1)) (eqs. R1-R2) placed at the wrapped
-// positions of a zero row of length N_v, transformed along v (e^{-2 pi i}).
-// Output T[p][row][b], all N_v columns.
+// positions of a zero row of length N_v, transformed along v (e^{-2 pi i});
+// the last FFT pass writes T[p][row][b], all N_v columns.
 template <typename R, int NTH>
 __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil, const double *__restrict__ nm1,
                                                      Cx<R> *__restrict__ T, PassGeom pg, int j_lo, int np,
@@ -544,10 +560,12 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
     const double *nrow = nm1 + (int64_t)row * pg.npix_y;
     for (int p = 0; p < np; ++p) {
         const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
+        C *dst = T + ((int64_t)p * pg.npix_x + row) * pg.nv;
         for (int b = threadIdx.x; b < pg.nv; b += NTH) {
-            int q = b < pg.nv - h ? b + h : b - (pg.nv - h);   // inverse of b = (q - h) mod N_v
+            // grid position b holds image column q with b = (q - h) mod N_v
+            const int q = b < pg.nv - h ? b + h : b - (pg.nv - h);
             C v = cmake<C>((R)0, (R)0);
-            if (q >= 0 && q < pg.npix_y && (b < pg.npix_y - h || b >= pg.nv - h)) {
+            if (q < pg.npix_y && (b < pg.npix_y - h || b >= pg.nv - h)) {
                 const R x = irow[q];
                 if (pg.do_w) {
                     double ph = cj * nrow[q];
@@ -560,12 +578,14 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
                     v = cmake<C>(x, (R)0);
                 }
             }
-            buf[b] = v;
+            buf[fft_lidx(b)] = v;
         }
         __syncthreads();
-        lds_fft<-1>(buf, 1, fd, tw, threadIdx.x, NTH);
-        C *dst = T + ((int64_t)p * pg.npix_x + row) * pg.nv;
-        for (int b = threadIdx.x; b < pg.nv; b += NTH) dst[b] = buf[b];
+        // an opaque copy of the descriptor per plane (see k_cols_grid)
+        FftDesc fp = fd;
+        fp.n = __builtin_amdgcn_readfirstlane(fp.n);
+        asm volatile("" : "+s"(fp.n));
+        lds_fft<true, false, -1, NTH>(buf, 1, fp, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
         __syncthreads();
     }
 }
@@ -588,23 +608,19 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
     const int kk = min(K, pg.nv - b0);
     const int h = pg.npix_x / 2;
     const C *src = T + (int64_t)p * pg.npix_x * pg.nv;
-    for (int e = threadIdx.x; e < pg.nu * K; e += NTH) {
-        const int a = e / K, col = e - a * K;
-        // a = (pp - h) mod N_u  <=>  pp = a + h (a < npix_x - h) or a - (N_u - h) (a >= N_u - h)
-        int pp = -1;
-        if (a < pg.npix_x - h) pp = a + h;
-        else if (a >= pg.nu - h) pp = a - (pg.nu - h);
-        C v = cmake<C>((R)0, (R)0);
-        if (pp >= 0 && col < kk) v = src[(int64_t)pp * pg.nv + b0 + col];
-        buf[e] = v;
-    }
-    __syncthreads();
-    lds_fft<-1>(buf, K, fd, tw, threadIdx.x, NTH);
     C *dst = G + (int64_t)p * pg.nu * pg.nv;
-    for (int e = threadIdx.x; e < pg.nu * kk; e += NTH) {
-        const int a = e / kk, col = e - a * kk;
-        dst[(int64_t)a * pg.nv + b0 + col] = buf[a * K + col];
-    }
+    lds_fft<false, false, -1, NTH>(
+        buf, K, fd, tw,
+        [&](int a, int col) {
+            // a = (pp - h) mod N_u  <=>  pp = a + h (a < npix_x - h) or a - (N_u - h) (a >= N_u - h)
+            int pp = -1;
+            if (a < pg.npix_x - h) pp = a + h;
+            else if (a >= pg.nu - h) pp = a - (pg.nu - h);
+            return (pp >= 0 && col < kk) ? src[(int64_t)pp * pg.nv + b0 + col] : cmake<C>((R)0, (R)0);
+        },
+        [&](int o, int col, C v, int) {
+            if (col < kk) dst[(int64_t)o * pg.nv + b0 + col] = v;
+        });
 }
 
 // ---- image-side elementwise kernels ----------------------------------------

@@ -147,16 +147,25 @@ int64_t grid_blocks(int64_t n, int threads, int64_t cap = 65536) {
     return std::max<int64_t>(1, std::min(b, cap));
 }
 
+// Radices of the passes: greedy over the register DFTs, largest first, so
+// that few passes (LDS exchanges) remain; the largest radix goes last (its
+// outputs are stored straight to the destination).
 void make_fft_desc(int n, FftDesc &d) {
     d.n = n;
     d.npass = 0;
     int m = n;
-    for (int r : {8, 4, 2, 5, 3, 7}) {
-        while (m % r == 0 && d.npass < kFftMaxPass) {
-            d.radix[d.npass++] = r;
-            m /= r;
-        }
+    while (m > 1 && d.npass < kFftMaxPass) {
+        int pick = 0;
+        for (int r : {16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2})
+            if (m % r == 0) {
+                pick = r;
+                break;
+            }
+        if (!pick) break;
+        d.radix[d.npass++] = pick;
+        m /= pick;
     }
+    std::reverse(d.radix, d.radix + d.npass);
 }
 
 // exp(-2 pi i t / N) with the angle folded into [0, pi/4] so that the library
@@ -483,7 +492,9 @@ int plan_build(wg_plan *p) {
     // columns per workgroup in the strided passes: fill up to 96 KB of LDS
     // (FP32 <= 12288 values = 512 threads x kFftMaxC, FP64 <= 6144 = 256 x kFftMaxC)
     p->k_cols = 1;
-    while (p->k_cols < 8 && (size_t)g.nu * (2 * p->k_cols) * sc <= 96 * 1024) p->k_cols *= 2;
+    // (the gridding column pass also keeps npix_x * K image sums in LDS)
+    while (p->k_cols < 8 && (size_t)(fft_lds_len(g.nu) * sc + d.npix_x * sr) * (2 * p->k_cols) <= 144 * 1024)
+        p->k_cols *= 2;
     // planes per batch: the gridder keeps one register accumulator per plane
     // of the batch and lane, P = alpha (a visibility's alpha planes then meet
     // at most two batches); the degridder stages P planes of tile + halo.
@@ -667,26 +678,27 @@ void launch_vis_kernel(bool gridding, const wg_plan *p, const VisArgs<R> &va, in
 
 template <typename R, int NTH> struct FftLaunch {
     static void rows_grid(const wg_plan *p, const Cx<R> *G, Cx<R> *T, const PassGeom &pg, int np, hipStream_t st) {
-        hipLaunchKernelGGL((k_rows_grid<R, NTH>), dim3(p->g.nu, np), dim3(NTH), p->g.nv * sizeof(Cx<R>), st, G, T,
+        hipLaunchKernelGGL((k_rows_grid<R, NTH>), dim3(p->g.nu, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st, G, T,
                            pg, p->fft_v, (const Cx<R> *)p->tw_v);
     }
     static void cols_grid(const wg_plan *p, const Cx<R> *T, R *acc, const PassGeom &pg, int j_lo, int np,
                           hipStream_t st) {
         const int K = p->k_cols;
         const int nb = ((p->g.npix_y + K - 1) / K + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_cols_grid<R, NTH>), dim3(nb), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>), st, T,
+        const size_t lds = (size_t)fft_lds_len(p->g.nu) * K * sizeof(Cx<R>) + (size_t)p->g.npix_x * K * sizeof(R);
+        hipLaunchKernelGGL((k_cols_grid<R, NTH>), dim3(nb), dim3(NTH), lds, st, T,
                            acc, p->nm1, pg, K, j_lo, np, p->fft_u, (const Cx<R> *)p->tw_u);
     }
     static void rows_degrid(const wg_plan *p, const R *itil, Cx<R> *T, const PassGeom &pg, int j_lo, int np,
                             hipStream_t st) {
-        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x), dim3(NTH), p->g.nv * sizeof(Cx<R>), st,
+        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
                            itil, p->nm1, T, pg, j_lo, np, p->fft_v, (const Cx<R> *)p->tw_v);
     }
     static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
                             hipStream_t st) {
         const int K = p->k_cols;
         const int nb = ((p->g.nv + K - 1) / K + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_cols_degrid<R, NTH>), dim3(nb, np), dim3(NTH), (size_t)p->g.nu * K * sizeof(Cx<R>),
+        hipLaunchKernelGGL((k_cols_degrid<R, NTH>), dim3(nb, np), dim3(NTH), (size_t)fft_lds_len(p->g.nu) * K * sizeof(Cx<R>),
                            st, T, G, pg, K, p->fft_u, (const Cx<R> *)p->tw_u);
     }
 };

@@ -99,6 +99,32 @@ def test_same_plan_as_o2(dev, alpha, sigma, prec):
     res["plan"].close()
 
 
+@pytest.mark.parametrize("npix,sigma,n_grid", [
+    (32, 1.5, 48), (64, 1.25, 80), (64, 1.5, 96), (56, 2.0, 112), (64, 2.0, 128), (96, 1.5, 144),
+    (128, 1.25, 160), (128, 1.5, 192), (112, 2.0, 224), (160, 1.5, 240), (128, 2.0, 256), (192, 1.5, 288),
+    (224, 1.5, 336), (288, 1.5, 432), (320, 1.5, 480), (512, 1.25, 640), (448, 1.5, 672), (480, 1.5, 720)])
+def test_fft_lengths_same_plan_as_o2(dev, npix, sigma, n_grid):
+    """Grid sizes whose FFTs take every register radix (2 ... 16, composite
+    ones included) and 2 to 3 passes: both directions against O2 at the
+    same plan (FP64, agreement to the kernel's polynomial error)."""
+    rng = np.random.default_rng(npix)
+    pix = 0.5 * math.pi / (180 * 60)
+    a = (299792458.0 / 1e9) / (2 * pix)
+    uvw = rng.uniform(-a, a, (300, 3))
+    uvw[:, 2] *= 0.05
+    case = dict(uvw=uvw, freq=np.array([1e9]), npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix,
+                vis=synth.complex_gaussian(rng, (300, 1)), dirty=rng.standard_normal((npix, npix)))
+    print(f"[fft] npix={npix} sigma={sigma}", flush=True)
+    res = run_product(case, 1e-2, "f64", torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=8, sigma=sigma)
+    assert res["info"]["nu"] == n_grid and res["info"]["nv"] == n_grid
+    pl = oracle_plan_from(res["info"], case)
+    d2 = o2.degrid(case["uvw"], case["freq"], case["dirty"], pl)
+    i2 = o2.grid(case["uvw"], case["freq"], case["vis"], pl)
+    assert rel(res["vis"], d2) < pl["eps_k"]
+    assert rel(res["img"], i2) < pl["eps_k"]
+    res["plan"].close()
+
+
 @pytest.mark.parametrize("ppb", [1, 2, 3])
 def test_batch_boundaries(dev, ppb):
     """Forcing few planes per batch moves visibilities across batch
