@@ -24,7 +24,8 @@ namespace wg {
 
 constexpr int kFftMaxPass = 16;
 constexpr int kFftMaxC = 24;      // complex values a thread holds per pass (N * K <= threads * kFftMaxC)
-constexpr int kFftMaxSlots = 32;  // last-pass outputs per thread: ceil(kFftMaxC / R) * R <= 32 for R <= 16
+constexpr int kFftMaxSlots = 32;
+  // last-pass outputs per thread: ceil(kFftMaxC / R) * R <= 32 for R <= 16
 
 // LDS words for length n (pad included)
 __host__ __device__ constexpr int fft_lds_len(int n) { return n + n / 16; }
@@ -266,7 +267,7 @@ template <int DIR, typename C> struct Dft<16, DIR, C> : DftComp<4, 4, DIR, C> {}
 // for a given (thread, output) so that callers may keep per-output
 // registers.  Barriers: a pass that reads and then writes LDS synchronises
 // in between; a pass that writes LDS synchronises after.
-template <int RADIX, int DIR, int NTH, bool first, bool last, typename C, typename Load, typename Store>
+template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
                                          Store &store) {
     constexpr int MAXB = (kFftMaxC + RADIX - 1) / RADIX;
@@ -275,6 +276,22 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
     const int W = M * K;
     const int tstride = N / (Ns * RADIX);
     C v[MAXB][RADIX];
+    // PF (FP32): twiddles first, so that their global reads overlap the LDS
+    // reads and the barrier (the first pass has none: Ns = 1); worth its
+    // registers where few workgroups share a CU (the column passes)
+    constexpr bool prefetch = PF && sizeof(C) == 8;
+    C t[prefetch ? MAXB : 1][RADIX - 1];
+    if constexpr (!first && prefetch) {
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) {
+            const int w = tid + b * NTH;
+            if (w < W) {
+                const int jm = (w / K) % Ns;
+#pragma unroll
+                for (int r = 1; r < RADIX; ++r) t[b][r - 1] = tw[jm * r * tstride];
+            }
+        }
+    }
     if constexpr (first) {
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) {
@@ -303,11 +320,11 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
         if (w < W) {
             const int j = w / K, col = w - j * K;
             const int jm = j % Ns;
-            if (Ns > 1) {
+            if constexpr (!first) {
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
-                    const C t = tw[jm * r * tstride];
-                    v[b][r] = DIR < 0 ? cmul(v[b][r], t) : cmulconj(v[b][r], t);
+                    const C tr = prefetch ? t[prefetch ? b : 0][r - 1] : tw[jm * r * tstride];
+                    v[b][r] = DIR < 0 ? cmul(v[b][r], tr) : cmulconj(v[b][r], tr);
                 }
             }
             Dft<RADIX, DIR, C>::run(v[b]);
@@ -329,49 +346,49 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
 struct NoIo {
     template <typename... A> __device__ __forceinline__ void operator()(A...) const {}
 };
-template <int RADIX, int DIR, int NTH, typename C>
+template <int RADIX, int DIR, int NTH, bool PF, typename C>
 __device__ __noinline__ void fft_pass_mid(C *buf, int N, int K, int Ns, const C *__restrict__ tw) {
     NoIo none;
-    fft_pass<RADIX, DIR, NTH, false, false>(buf, N, K, Ns, tw, none, none);
+    fft_pass<RADIX, DIR, NTH, false, false, PF>(buf, N, K, Ns, tw, none, none);
 }
 
 // one pass of runtime radix r with compile-time role
-template <int DIR, int NTH, bool first, bool last, typename C, typename Load, typename Store>
+template <int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, const C *__restrict__ tw,
                                            Load &load, Store &store) {
     if constexpr (!first && !last) {
         switch (r) {
-            case 16: fft_pass_mid<16, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 15: fft_pass_mid<15, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 14: fft_pass_mid<14, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 12: fft_pass_mid<12, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 10: fft_pass_mid<10, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 9: fft_pass_mid<9, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 8: fft_pass_mid<8, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 7: fft_pass_mid<7, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 6: fft_pass_mid<6, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 5: fft_pass_mid<5, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 4: fft_pass_mid<4, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 3: fft_pass_mid<3, DIR, NTH>(buf, N, K, Ns, tw); break;
-            case 2: fft_pass_mid<2, DIR, NTH>(buf, N, K, Ns, tw); break;
+            case 16: fft_pass_mid<16, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 15: fft_pass_mid<15, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 14: fft_pass_mid<14, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 12: fft_pass_mid<12, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 10: fft_pass_mid<10, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 9: fft_pass_mid<9, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 8: fft_pass_mid<8, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 7: fft_pass_mid<7, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 6: fft_pass_mid<6, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 5: fft_pass_mid<5, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 4: fft_pass_mid<4, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 3: fft_pass_mid<3, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 2: fft_pass_mid<2, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
             default: break;
         }
         return;
     }
     switch (r) {
-        case 16: fft_pass<16, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 15: fft_pass<15, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 14: fft_pass<14, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 12: fft_pass<12, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 10: fft_pass<10, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 9: fft_pass<9, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 8: fft_pass<8, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 7: fft_pass<7, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 6: fft_pass<6, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 5: fft_pass<5, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 4: fft_pass<4, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 3: fft_pass<3, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
-        case 2: fft_pass<2, DIR, NTH, first, last>(buf, N, K, Ns, tw, load, store); break;
+        case 16: fft_pass<16, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 15: fft_pass<15, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 14: fft_pass<14, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 12: fft_pass<12, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 10: fft_pass<10, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 9: fft_pass<9, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 8: fft_pass<8, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 7: fft_pass<7, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 6: fft_pass<6, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 5: fft_pass<5, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 4: fft_pass<4, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 3: fft_pass<3, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 2: fft_pass<2, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
         default: break;
     }
 }
@@ -383,21 +400,22 @@ __device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, 
 // buf[fft_lidx(o) * K + col] (synchronised); otherwise the last pass calls
 // store(o, col, value, slot).  buf holds fft_lds_len(d.n) * K complex
 // values.  The caller must synchronise between two calls that share buf.
+// PF: prefetch each pass's twiddles (FP32 only).
 // Passes that only move data between LDS buffers run as functions of their
 // own (fft_pass_mid), which keeps each pass's register allocation apart.
-template <bool IN_LDS, bool OUT_LDS, int DIR, int NTH, typename C, typename Load, typename Store>
+template <bool IN_LDS, bool OUT_LDS, int DIR, int NTH, bool PF, typename C, typename Load, typename Store>
 __device__ __forceinline__ void lds_fft(C *buf, int K, const FftDesc &d, const C *__restrict__ tw, Load &&load,
                                         Store &&store) {
     // d.npass >= 2: every length here is a multiple of 16 and at least 48
-    if constexpr (IN_LDS) fft_pass_r<DIR, NTH, false, false>(d.radix[0], buf, d.n, K, 1, tw, load, store);
-    else fft_pass_r<DIR, NTH, true, false>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    if constexpr (IN_LDS) fft_pass_r<DIR, NTH, false, false, PF>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    else fft_pass_r<DIR, NTH, true, false, PF>(d.radix[0], buf, d.n, K, 1, tw, load, store);
     int Ns = d.radix[0];
     for (int s = 1; s < d.npass - 1; ++s) {
-        fft_pass_r<DIR, NTH, false, false>(d.radix[s], buf, d.n, K, Ns, tw, load, store);
+        fft_pass_r<DIR, NTH, false, false, PF>(d.radix[s], buf, d.n, K, Ns, tw, load, store);
         Ns *= d.radix[s];
     }
-    if constexpr (OUT_LDS) fft_pass_r<DIR, NTH, false, false>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
-    else fft_pass_r<DIR, NTH, false, true>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
+    if constexpr (OUT_LDS) fft_pass_r<DIR, NTH, false, false, PF>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
+    else fft_pass_r<DIR, NTH, false, true, PF>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
 }
 
 }  // namespace wg

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, 
     const C *src = G + ((int64_t)p * pg.nu + a) * pg.nv;
     C *dst = T + ((int64_t)p * pg.nu + a) * pg.npix_y;
     const int h = pg.npix_y / 2;
-    lds_fft<false, false, +1, NTH>(
+    lds_fft<false, false, +1, NTH, false>(
         buf, 1, fd, tw, [&](int n, int) { return src[n]; },
         [&](int o, int, C v, int) {
             // output frequency o holds image column q with o = (q - h) mod N_v
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
         // hoisted out of the plane loop and held in registers across it
         int Kp = __builtin_amdgcn_readfirstlane(K);
         asm volatile("" : "+s"(Kp));
-        lds_fft<false, true, +1, NTH>(
+        lds_fft<false, true, +1, NTH, true>(
             buf, Kp, fd, tw,
             [&](int n, int col) {
                 return col < kk ? src[(int64_t)n * pg.npix_y + q0 + col] : cmake<C>((R)0, (R)0);
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
         FftDesc fp = fd;
         fp.n = __builtin_amdgcn_readfirstlane(fp.n);
         asm volatile("" : "+s"(fp.n));
-        lds_fft<true, false, -1, NTH>(buf, 1, fp, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
+        lds_fft<true, false, -1, NTH, false>(buf, 1, fp, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
         __syncthreads();
     }
 }
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
     const int h = pg.npix_x / 2;
     const C *src = T + (int64_t)p * pg.npix_x * pg.nv;
     C *dst = G + (int64_t)p * pg.nu * pg.nv;
-    lds_fft<false, false, -1, NTH>(
+    lds_fft<false, false, -1, NTH, true>(
         buf, K, fd, tw,
         [&](int a, int col) {
             // a = (pp - h) mod N_u  <=>  pp = a + h (a < npix_x - h) or a - (N_u - h) (a >= N_u - h)
