@@ -543,7 +543,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     }
 }
 
-// Degridding pass A: image row p, for every plane of the batch: screened
+// Degridding pass A: image row p, one plane of the batch per workgroup: screened
 // row I~ exp(+2 pi i c_j (n - 1)) (eqs. R1-R2) placed at the wrapped
 // positions of a zero row of length N_v, transformed along v (e^{-2 pi i});
 // the last FFT pass writes T[p][row][b], all N_v columns.
@@ -558,7 +558,8 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
     const int h = pg.npix_y / 2;
     const R *irow = itil + (int64_t)row * pg.npix_y;
     const double *nrow = nm1 + (int64_t)row * pg.npix_y;
-    for (int p = 0; p < np; ++p) {
+    {
+        const int p = blockIdx.y;
         const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
         C *dst = T + ((int64_t)p * pg.npix_x + row) * pg.nv;
         for (int b = threadIdx.x; b < pg.nv; b += NTH) {
@@ -581,12 +582,7 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
             buf[fft_lidx(b)] = v;
         }
         __syncthreads();
-        // an opaque copy of the descriptor per plane (see k_cols_grid)
-        FftDesc fp = fd;
-        fp.n = __builtin_amdgcn_readfirstlane(fp.n);
-        asm volatile("" : "+s"(fp.n));
-        lds_fft<true, false, -1, NTH, false>(buf, 1, fp, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
-        __syncthreads();
+        lds_fft<true, false, -1, NTH, false>(buf, 1, fd, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
     }
 }
 

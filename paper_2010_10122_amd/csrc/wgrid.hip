@@ -691,7 +691,7 @@ template <typename R, int NTH> struct FftLaunch {
     }
     static void rows_degrid(const wg_plan *p, const R *itil, Cx<R> *T, const PassGeom &pg, int j_lo, int np,
                             hipStream_t st) {
-        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
+        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
                            itil, p->nm1, T, pg, j_lo, np, p->fft_v, (const Cx<R> *)p->tw_v);
     }
     static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
