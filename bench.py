@@ -236,6 +236,59 @@ def differentiation(dev, gd_steps=50, seed=5):
     return out
 
 
+def large_workload(dev):
+    """Large workload: 8192^2 image over 30 deg, 256 antennas (log-radial to
+    10 km), 4 h in 1000 dumps x 8 channels = 261,120,000 visibilities, FP32 at
+    eps = 1e-5 (about 12,500 w-planes).  One degrid and one grid after a
+    warm-up of each; Mvis/s and the whole-apply fraction of the HBM roofline
+    (algorithmic bytes of the plan / time / 8 TB/s)."""
+    import torch
+
+    import paper_2010_10122_amd as wg
+    import synth
+
+    t0 = time.perf_counter()
+    c = synth.large()
+    print(f"[bench] large workload generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    uvw = torch.from_numpy(c["uvw"]).to(dev)
+    freq = torch.from_numpy(c["freq"]).to(dev)
+    dirty = torch.from_numpy(c["dirty"]).to(dev)
+    vis = torch.from_numpy(c["vis"]).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = wg.Plan(uvw, freq, c["npix_x"], c["npix_y"], c["pixsize_x"], c["pixsize_y"], 1e-5, "f32")
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    print(f"[bench] large plan alpha={info['alpha']} sigma={info['sigma']} N={info['nu']} Nw={info['nw']} "
+          f"in {plan_s:.1f} s", file=sys.stderr, flush=True)
+    # one timed application per direction (each runs tens of seconds)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    t_op = {}
+    for name in ("degrid", "grid"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "degrid":
+            plan.degrid(dirty, workspace=ws)
+        else:
+            plan.grid(vis, workspace=ws)
+        torch.cuda.synchronize()
+        t_op[name] = time.perf_counter() - t0
+        print(f"[bench] large {name}: {t_op[name]:.2f} s", file=sys.stderr, flush=True)
+    t_deg, t_grid = t_op["degrid"], t_op["grid"]
+    n_vis = info["n_vis"]
+    plan.close()
+    out = {"workload": f"large: 8192^2 image, 30 deg, {c['uvw'].shape[0]} rows x {len(c['freq'])} ch = {n_vis} vis, "
+                       "eps=1e-5 FP32",
+           "alpha": info["alpha"], "sigma": info["sigma"], "nu": info["nu"], "nw": info["nw"],
+           "plan_ms": round(plan_s * 1e3, 1), "degrid_ms": round(t_deg * 1e3, 1), "grid_ms": round(t_grid * 1e3, 1),
+           "degrid_mvis_s": round(n_vis / t_deg / 1e6, 2), "grid_mvis_s": round(n_vis / t_grid / 1e6, 2),
+           "degrid_hbm_frac": round(info["bytes_degrid"] / t_deg / 1e9 / HBM_PEAK_GBS, 4),
+           "grid_hbm_frac": round(info["bytes_grid"] / t_grid / 1e9 / HBM_PEAK_GBS, 4)}
+    print(f"[bench] large: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def time_operator(plan, dirty, vis, steps, warmup, prof=None):
     import torch
     for _ in range(warmup):
@@ -275,6 +328,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--dumps", type=int, default=2880, help="time dumps (2880 = the full 8 h workload)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the large workload (8192^2, 261M visibilities; adds about two minutes)")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving workload run after the operator timing (0 = skip)")
     args = ap.parse_args()
@@ -305,9 +360,10 @@ def main():
     del calib, calib_out
     res = {}
     prof = wg.Profiler()
-    for prec, eps, steps in (("f32", 1e-5, args.steps), ("f64", 1e-5, args.fp64_steps)):
-        if prec == "f64" and args.no_fp64:
-            continue
+    legs = [("f32", "f32", 1e-5, args.steps)]
+    if not args.no_fp64:
+        legs += [("f64", "f64", 1e-5, args.fp64_steps), ("f64_1e-10", "f64", 1e-10, 1)]
+    for key, prec, eps, steps in legs:
         rdt = torch.float32 if prec == "f32" else torch.float64
         cdt = torch.complex64 if prec == "f32" else torch.complex128
         dirty = torch.from_numpy(case["dirty"]).to(dev, rdt)
@@ -323,13 +379,13 @@ def main():
         with prof:
             t_deg, t_grid, wall, out_v = time_operator(plan, dirty, vis, steps, args.warmup, prof)
         kern = prof.read()
-        print(f"[bench] {prec}: degrid {t_deg * 1e3:.1f} ms, grid {t_grid * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] {key}: degrid {t_deg * 1e3:.1f} ms, grid {t_grid * 1e3:.1f} ms", file=sys.stderr, flush=True)
         # keep a sample of this very output for the accuracy check of the
         # CPU-baseline leg (degrid of 2000 random visibilities)
         idx = np.random.default_rng(7).choice(n_vis, size=2000, replace=False)
         sample = out_v.reshape(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
-        res[prec] = dict(info=info, t_deg=t_deg, t_grid=t_grid, wall=wall, steps=steps, plan_s=plan_s,
-                         kernels=kern, sample_idx=idx, sample=sample)
+        res[key] = dict(info=info, t_deg=t_deg, t_grid=t_grid, wall=wall, steps=steps, plan_s=plan_s,
+                        kernels=kern, sample_idx=idx, sample=sample)
         plan.close()
         del dirty, vis
         torch.cuda.empty_cache()
@@ -382,14 +438,20 @@ def main():
         "kernels": per_kernel,
         "roofline": roof,
     }
-    if "f64" in res:
-        f = res["f64"]
-        out["fp64"] = {"grid_mvis_s": round(n_vis / f["t_grid"] / 1e6, 2),
-                       "degrid_mvis_s": round(n_vis / f["t_deg"] / 1e6, 2),
-                       "value": round(n_vis / (0.5 * (f["t_deg"] + f["t_grid"])) / 1e6, 2),
-                       "alpha": f["info"]["alpha"], "sigma": f["info"]["sigma"], "nu": f["info"]["nu"],
-                       "nw": f["info"]["nw"], "plan_ms": round(f["plan_s"] * 1e3, 1)}
+    for key, name in (("f64", "fp64"), ("f64_1e-10", "fp64_eps1e-10")):
+        if key not in res:
+            continue
+        f = res[key]
+        out[name] = {"epsilon": 1e-5 if key == "f64" else 1e-10,
+                     "grid_mvis_s": round(n_vis / f["t_grid"] / 1e6, 2),
+                     "degrid_mvis_s": round(n_vis / f["t_deg"] / 1e6, 2),
+                     "value": round(n_vis / (0.5 * (f["t_deg"] + f["t_grid"])) / 1e6, 2),
+                     "alpha": f["info"]["alpha"], "sigma": f["info"]["sigma"], "nu": f["info"]["nu"],
+                     "nw": f["info"]["nw"], "plan_ms": round(f["plan_s"] * 1e3, 1), "steps": f["steps"]}
+    if "fp64" in out:
         out["fp32_over_fp64"] = round(value / out["fp64"]["value"], 3)
+    if args.large:
+        out["large"] = large_workload(dev)
     if not args.no_diff:
         out["differentiation"] = differentiation(dev)
     if args.serve_requests > 0:
@@ -405,7 +467,8 @@ def main():
             ref = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"],
                              vis_idx=rr["sample_idx"])
             err = float(np.linalg.norm(rr["sample"] - ref) / np.linalg.norm(ref))
-            (out if prec == "f32" else out["fp64"])["degrid_rel_err_vs_oracle"] = err
+            (out if prec == "f32" else out["fp64" if prec == "f64" else "fp64_eps1e-10"])[
+                "degrid_rel_err_vs_oracle"] = err
         print(f"[bench] cpu baseline in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     prof.close()
     print(json.dumps(out), flush=True)
