@@ -79,6 +79,47 @@ template <typename R, int ALPHA, int PS> struct GridStage {
     static constexpr size_t bytes = off_cnt + (size_t)NREG * 4 * sizeof(int);
 };
 
+// Swaps across lane rows (gfx950 v_permlane32_swap / v_permlane16_swap):
+// swap32 exchanges lanes 32..63 of x with lanes 0..31 of y; swap16 exchanges
+// rows 1 and 3 of x with rows 0 and 2 of y.  FP64 values swap as two halves.
+__device__ __forceinline__ void swap32(float &x, float &y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float &x, float &y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(double &x, double &y) {
+    const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+    const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16(double &x, double &y) {
+    const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+    const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+// Row g of the result holds (a_g0 + a_g2) + (a_g1 + a_g3) for the value a
+// of region g: v0..v3 are the four regions' partial sums in every row.
+template <typename R> __device__ __forceinline__ R reduce_scatter4(R v0, R v1, R v2, R v3) {
+    swap32(v0, v2);               // v0: rows 0,1 of region 0 | rows 0,1 of region 2 ...
+    const R z0 = v0 + v2;         // rows 0,1: region 0 (g0+g2, g1+g3); rows 2,3: region 2
+    swap32(v1, v3);
+    const R z1 = v1 + v3;         // rows 0,1: region 1; rows 2,3: region 3
+    R a = z0, b = z1;
+    swap16(a, b);                 // a: rows (z0 r0, z1 r0, z0 r2, z1 r2); b: rows 1 / 3
+    return a + b;
+}
+
 // Block -> work item.  Blocks [0, pad8(n_extra)) take the listed extra items
 // (heaviest tiles first in dispatch order, dealt round-robin over the XCDs);
 // the following blocks take the first item of every tile, (tile, 0, cap, -1),
@@ -282,28 +323,15 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
         }
         __syncthreads();
     }
-    // reduce-scatter over the four lane groups: group k ends with the total
-    // of region k (exchange halves across groups k^2, then k^1)
-    const bool hi2 = (grp & 2) != 0, hi1 = (grp & 1) != 0;
+    // reduce-scatter over the four lane groups (rows of 16 lanes): group k
+    // ends with the total of region k.  The cross-row swaps (gfx950): the
+    // 32-lane swap leaves rows (0,1 | 2,3) of two values as (x | y) and
+    // (x' | y'), the 16-lane swap rows (0 | 2) and (1 | 3); one add after each.
     R tot_re[PS], tot_im[PS];
 #pragma unroll
     for (int r = 0; r < PS; ++r) {
-        R y_re[2], y_im[2];
-#pragma unroll
-        for (int q0 = 0; q0 < 2; ++q0) {
-            const R keep_re = hi2 ? acc_re[q0 + 2][r] : acc_re[q0][r];
-            const R send_re = hi2 ? acc_re[q0][r] : acc_re[q0 + 2][r];
-            const R keep_im = hi2 ? acc_im[q0 + 2][r] : acc_im[q0][r];
-            const R send_im = hi2 ? acc_im[q0][r] : acc_im[q0 + 2][r];
-            y_re[q0] = keep_re + __shfl_xor(send_re, 32);
-            y_im[q0] = keep_im + __shfl_xor(send_im, 32);
-        }
-        const R keep_re = hi1 ? y_re[1] : y_re[0];
-        const R send_re = hi1 ? y_re[0] : y_re[1];
-        const R keep_im = hi1 ? y_im[1] : y_im[0];
-        const R send_im = hi1 ? y_im[0] : y_im[1];
-        tot_re[r] = keep_re + __shfl_xor(send_re, 16);
-        tot_im[r] = keep_im + __shfl_xor(send_im, 16);
+        tot_re[r] = reduce_scatter4(acc_re[0][r], acc_re[1][r], acc_re[2][r], acc_re[3][r]);
+        tot_im[r] = reduce_scatter4(acc_im[0][r], acc_im[1][r], acc_im[2][r], acc_im[3][r]);
     }
     // lane group k stores region k of the wave's band: 4 rows x 16 columns
     const int np = j_hi - j_lo;
