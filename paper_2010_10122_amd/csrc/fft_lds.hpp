@@ -267,6 +267,37 @@ template <int DIR, typename C> struct Dft<16, DIR, C> : DftComp<4, 4, DIR, C> {}
 // for a given (thread, output) so that callers may keep per-output
 // registers.  Barriers: a pass that reads and then writes LDS synchronises
 // in between; a pass that writes LDS synchronises after.
+// Twiddles of a butterfly: w^r, r = 1 .. RADIX-1, with w = tw[jm * tstride].
+// Table reads are issued before the LDS reads and the barrier; the compact
+// form reads w, w^4 and w^8 only and forms the other powers by at most four
+// complex products (a few ulp in FP32; its registers stay few).
+template <int RADIX, typename C> struct TwPre {
+    C w1, w4, w8;
+};
+template <int RADIX, typename C>
+__device__ __forceinline__ TwPre<RADIX, C> tw_read(const C *__restrict__ tw, int e) {
+    TwPre<RADIX, C> t;
+    t.w1 = tw[e];
+    if constexpr (RADIX > 4) t.w4 = tw[4 * e];
+    if constexpr (RADIX > 8) t.w8 = tw[8 * e];
+    return t;
+}
+template <int RADIX, typename C> __device__ __forceinline__ void tw_powers(const TwPre<RADIX, C> &t, C *w) {
+    w[1] = t.w1;
+    if constexpr (RADIX > 2) w[2] = cmul(t.w1, t.w1);
+    if constexpr (RADIX > 3) w[3] = cmul(w[2], t.w1);
+    if constexpr (RADIX > 4) {
+        w[4] = t.w4;
+#pragma unroll
+        for (int r = 5; r < RADIX && r < 8; ++r) w[r] = cmul(t.w4, w[r - 4]);
+    }
+    if constexpr (RADIX > 8) {
+        w[8] = t.w8;
+#pragma unroll
+        for (int r = 9; r < RADIX; ++r) w[r] = cmul(t.w8, w[r - 8]);
+    }
+}
+
 template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
                                          Store &store) {
@@ -276,19 +307,26 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
     const int W = M * K;
     const int tstride = N / (Ns * RADIX);
     C v[MAXB][RADIX];
-    // PF (FP32): twiddles first, so that their global reads overlap the LDS
-    // reads and the barrier (the first pass has none: Ns = 1); worth its
-    // registers where few workgroups share a CU (the column passes)
-    constexpr bool prefetch = PF && sizeof(C) == 8;
-    C t[prefetch ? MAXB : 1][RADIX - 1];
-    if constexpr (!first && prefetch) {
+    // PF: every twiddle read up front (FP32 only; worth its registers where
+    // few workgroups share a CU, the column passes); otherwise the compact
+    // form above, also read up front
+    // (FP64: plain reads where they are used, to keep its registers)
+    constexpr bool full = PF && sizeof(C) == 8;
+    constexpr bool compact = !PF && sizeof(C) == 8;
+    C t[full ? MAXB : 1][RADIX - 1];
+    TwPre<RADIX, C> tp[compact ? MAXB : 1];
+    if constexpr (!first && (full || compact)) {
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) {
             const int w = tid + b * NTH;
             if (w < W) {
                 const int jm = (w / K) % Ns;
+                if constexpr (full) {
 #pragma unroll
-                for (int r = 1; r < RADIX; ++r) t[b][r - 1] = tw[jm * r * tstride];
+                    for (int r = 1; r < RADIX; ++r) t[b][r - 1] = tw[jm * r * tstride];
+                } else {
+                    tp[b] = tw_read<RADIX>(tw, jm * tstride);
+                }
             }
         }
     }
@@ -320,10 +358,20 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
         if (w < W) {
             const int j = w / K, col = w - j * K;
             const int jm = j % Ns;
-            if constexpr (!first) {
+            if constexpr (!first && (full || compact)) {
+                C wr[RADIX];
+                if constexpr (full) {
+#pragma unroll
+                    for (int r = 1; r < RADIX; ++r) wr[r] = t[full ? b : 0][r - 1];
+                } else {
+                    tw_powers<RADIX>(tp[compact ? b : 0], wr);
+                }
+#pragma unroll
+                for (int r = 1; r < RADIX; ++r) v[b][r] = DIR < 0 ? cmul(v[b][r], wr[r]) : cmulconj(v[b][r], wr[r]);
+            } else if constexpr (!first) {
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
-                    const C tr = prefetch ? t[prefetch ? b : 0][r - 1] : tw[jm * r * tstride];
+                    const C tr = tw[jm * r * tstride];
                     v[b][r] = DIR < 0 ? cmul(v[b][r], tr) : cmulconj(v[b][r], tr);
                 }
             }
