@@ -60,7 +60,7 @@ typedef struct {
     const double  *freq;         /* device [n_chan], channel frequencies in Hz (> 0)    */
     const uint8_t *mask;         /* device [n_rows][n_chan] or NULL; !=0 selects        */
     int64_t        n_rows;       /* >= 0                                                */
-    int64_t        n_chan;       /* >= 1; n_rows * n_chan < 2^32                        */
+    int64_t        n_chan;       /* >= 1; n_rows * n_chan < 2^31                        */
     int            npix_x;       /* image size, even and >= 32 (Appendix B)             */
     int            npix_y;
     double         pixsize_x;    /* pixel size in radians, > 0                          */
@@ -90,7 +90,7 @@ typedef struct {
  * Errors: WG_EINVAL for NULL desc/out/uvw/freq, odd or < 32 npix, pixsize
  *   <= 0, epsilon outside (2e-13, 0.1] (FP64) or [1e-5, 0.1] (FP32), a forced
  *   (alpha, sigma) not in the tables, any pixel with l^2 + m^2 >= 1,
- *   n_rows * n_chan >= 2^32; WG_EUNSUPPORTED when no printed kernel reaches
+ *   n_rows * n_chan >= 2^31; WG_EUNSUPPORTED when no printed kernel reaches
  *   epsilon or the grid exceeds the FFT size limit; WG_ENOMEM, WG_EHIP. */
 int wg_plan_create(const wg_plan_desc *desc, wg_plan **out);
 

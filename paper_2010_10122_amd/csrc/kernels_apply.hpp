@@ -680,15 +680,17 @@ __global__ void k_degrid_finish(const Cx<R> *__restrict__ visacc, const uint32_t
 // Gridding input in sorted order: weighted, and conjugated where folded.
 template <typename R>
 __global__ void k_gather_vis(const Cx<R> *__restrict__ vis, const R *__restrict__ wgt,
-                             const uint32_t *__restrict__ order, const int2 *__restrict__ anc, int64_t n_active,
-                             Cx<R> *__restrict__ vsorted) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t idx = order[s];
-        Cx<R> v = vis[idx];
-        if (wgt) v = cscale(v, wgt[idx]);
-        if (anc[s].y < 0) v.y = -v.y;
-        vsorted[s] = v;
+                             const uint32_t *__restrict__ inv, int64_t n_total, Cx<R> *__restrict__ vsorted) {
+    // caller's order in, sorted order out: the reads stay contiguous and the
+    // scattered side is the write (cheaper than a scattered read)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = inv[i];
+        if (e == 0xffffffffu) continue;                    // masked
+        Cx<R> v = vis[i];
+        if (wgt) v = cscale(v, wgt[i]);
+        if (e >> 31) v.y = -v.y;                            // folded: conjugate
+        vsorted[e & 0x7fffffffu] = v;
     }
 }
 

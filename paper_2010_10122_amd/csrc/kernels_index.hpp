@@ -269,6 +269,22 @@ __global__ void k_items(const uint32_t *__restrict__ tab_lo, const uint32_t *__r
     }
 }
 
+// ---- inverse permutation ----------------------------------------------------
+// inv[r * n_chan + c] = sorted position | fold << 31 for selected
+// visibilities, ~0 for masked ones (filled beforehand), so that gridding can
+// read its input in the caller's order and scatter it to sorted order.
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t value) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = value;
+}
+
+__global__ void k_inv_order(const uint32_t *__restrict__ order, const int2 *__restrict__ anc, int64_t n_active,
+                            uint32_t *__restrict__ inv) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
+         s += (int64_t)gridDim.x * blockDim.x)
+        inv[order[s]] = (uint32_t)s | (anc[s].y < 0 ? 0x80000000u : 0u);
+}
+
 // ---- per sorted visibility: kernel-local coordinates and anchors ------------
 // z = 2 (first cell - coordinate + alpha/2) - 1 in [-1, 1) for u, v and w
 // (the shared local variable of the alpha polynomial pieces), anchors packed

@@ -225,6 +225,7 @@ struct wg_plan {
     uint32_t *tab_lo = nullptr, *tab_hi = nullptr;
     void *zc = nullptr;                // [n_active][3] R: kernel-local coordinates
     int2 *anc = nullptr;               // [n_active] anchors and fold bit
+    uint32_t *inv = nullptr;           // [n_total] sorted position | fold << 31, ~0 if masked
     // extra work items per batch (lists longer than the item cap); offsets into
     // the device lists, [NJ + 1] each
     std::vector<uint32_t> xg_off, xd_off, xr_off;
@@ -385,7 +386,7 @@ int validate(const wg_plan_desc *d) {
     if (!d) return WG_EINVAL;
     if (d->n_rows < 0 || d->n_chan < 1) return WG_EINVAL;
     if ((d->n_rows > 0 && !d->uvw) || !d->freq) return WG_EINVAL;
-    if ((unsigned long long)d->n_rows * (unsigned long long)d->n_chan >= (1ULL << 32)) return WG_EINVAL;
+    if ((unsigned long long)d->n_rows * (unsigned long long)d->n_chan >= (1ULL << 31)) return WG_EINVAL;
     if (d->npix_x < 32 || d->npix_y < 32 || (d->npix_x & 1) || (d->npix_y & 1)) return WG_EINVAL;
     if (!(d->pixsize_x > 0.0) || !(d->pixsize_y > 0.0)) return WG_EINVAL;
     if (d->precision != WG_F32 && d->precision != WG_F64) return WG_EINVAL;
@@ -589,8 +590,19 @@ int plan_build(wg_plan *p) {
                                0, st, d.uvw, p->scale, p->order, p->n_active, g, (double *)p->zc, p->anc);
         LAUNCH_CHECK("k_vis_prep");
     }
+    // inverse permutation (caller's order -> sorted position and fold bit)
+    p->inv = (uint32_t *)p->mem.get(std::max<int64_t>(p->n_total, 1) * sizeof(uint32_t));
+    if (!p->inv) return WG_ENOMEM;
+    if (p->n_total > 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 20)), dim3(256), 0, st,
+                           p->inv, p->n_total, 0xffffffffu);
+        if (p->n_active > 0)
+            hipLaunchKernelGGL(k_inv_order, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 20)), dim3(256), 0,
+                               st, p->order, p->anc, p->n_active, p->inv);
+        LAUNCH_CHECK("k_inv_order");
+    }
     p->index_bytes += nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t) +
-                      nact * (3 * sr + sizeof(int2));
+                      nact * (3 * sr + sizeof(int2)) + std::max<int64_t>(p->n_total, 1) * sizeof(uint32_t);
     HIP_TRY(hipStreamSynchronize(st));
     p->mem.put(dpx);
     p->mem.put(dpy);
@@ -765,8 +777,8 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
         if (p->n_active > 0) {
             {
                 ProfScope ps(WG_KIND_VIS, st);
-                hipLaunchKernelGGL(k_gather_vis<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
-                                   0, st, (const C *)in, (const R *)wgt, p->order, p->anc, p->n_active, vacc);
+                hipLaunchKernelGGL(k_gather_vis<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256),
+                                   0, st, (const C *)in, (const R *)wgt, p->inv, p->n_total, vacc);
             }
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;

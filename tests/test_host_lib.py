@@ -121,7 +121,8 @@ def test_plan_create_rejects_invalid_arguments_before_device_work():
     bad = [dict(npix_x=63), dict(npix_y=30), dict(pixsize_x=0.0), dict(epsilon=1e-6),
            dict(epsilon=1e-14, precision=_lib.WG_F64), dict(epsilon=0.5), dict(precision=7),
            dict(n_chan=0), dict(n_rows=-1), dict(uvw=None), dict(freq=None),
-           dict(n_rows=2 ** 31, n_chan=2), dict(alpha=12, sigma=1.85), dict(alpha=9, sigma=1.5),
+           dict(n_rows=2 ** 31, n_chan=2), dict(n_rows=2 ** 30, n_chan=2), dict(alpha=12, sigma=1.85),
+           dict(alpha=9, sigma=1.5),
            dict(pixsize_x=0.03, pixsize_y=0.03), dict(planes_per_batch=-2)]
     for kw in bad:
         h = ctypes.c_void_p()
