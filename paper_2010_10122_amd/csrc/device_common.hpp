@@ -130,6 +130,25 @@ __device__ __forceinline__ void kernel_values_z(R z, const R *__restrict__ coef,
     }
 }
 
+// The same for the u, v and w coordinates of one visibility at once: one
+// read of each coefficient row serves all three (3 alpha independent Horner
+// chains per step).
+template <int ALPHA, typename R>
+__device__ __forceinline__ void kernel_values_z3(R zu, R zv, R zw, const R *__restrict__ coef, int degree,
+                                                 R ku[ALPHA], R kv[ALPHA], R kw[ALPHA]) {
+#pragma unroll
+    for (int i = 0; i < ALPHA; ++i) ku[i] = kv[i] = kw[i] = coef[degree * ALPHA + i];
+    for (int d = degree - 1; d >= 0; --d) {
+#pragma unroll
+        for (int i = 0; i < ALPHA; ++i) {
+            const R c = coef[d * ALPHA + i];
+            ku[i] = ku[i] * zu + c;
+            kv[i] = kv[i] * zv + c;
+            kw[i] = kw[i] * zw + c;
+        }
+    }
+}
+
 // blockIdx -> work-item remap that keeps neighbouring tiles on one XCD:
 // workgroups are dealt round-robin over the 8 XCDs, so give XCD x the
 // contiguous range [x * per, (x + 1) * per).  Returns -1 for padding blocks.

@@ -230,8 +230,7 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             s_d[tid] = a.vsorted[s];
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z<ALPHA, R>(zu, a.coef, a.degree, ku);
-            kernel_values_z<ALPHA, R>(zv, a.coef, a.degree, kv);
+            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, a.coef, a.degree, ku, kv, kw);
             R *pu = s_ku + tid * KP;
             R *pv = s_kv + tid * KP;
 #pragma unroll
@@ -246,7 +245,6 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             }
             // plane slot rr holds plane j_lo + rr; kernel index j - iw
             if (g.do_w) {
-                kernel_values_z<ALPHA, R>(zw, a.coef, a.degree, kw);
                 const int sh = j_lo - iw;                      // kernel index of slot 0
 #pragma unroll
                 for (int rr = 0; rr < PS; ++rr) {
@@ -436,11 +434,8 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
             if (jw0 >= jw1) continue;
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z<ALPHA, R>(zu, a.coef, a.degree, ku);
-            kernel_values_z<ALPHA, R>(zv, a.coef, a.degree, kv);
-            if (g.do_w) {
-                kernel_values_z<ALPHA, R>(zw, a.coef, a.degree, kw);
-            } else {
+            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, a.coef, a.degree, ku, kv, kw);
+            if (!g.do_w) {
 #pragma unroll
                 for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
             }
