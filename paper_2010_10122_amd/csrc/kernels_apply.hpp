@@ -408,9 +408,17 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
     if (s0 >= s1) return;
     const int tid = threadIdx.x;
     const int j_lo = J * a.P;
-    const int j_hi = min(j_lo + a.P, g.nw);
+    int j_hi = min(j_lo + a.P, g.nw);
+    int j_first = j_lo;
+    if (g.do_w) {
+        // the run is sorted by first plane: only planes from the first
+        // visibility's to the last one's footprint are read
+        const int iw0 = a.anc[s0].y & 0x7fffffff, iw1 = a.anc[s1 - 1].y & 0x7fffffff;
+        j_first = max(j_lo, iw0);
+        j_hi = min(j_hi, iw1 + ALPHA);
+    }
     // planes are staged PD at a time (tile + halo of PD planes in LDS)
-    for (int g0 = j_lo; g0 < j_hi; g0 += PD) {
+    for (int g0 = j_first; g0 < j_hi; g0 += PD) {
         const int g1 = min(g0 + PD, j_hi);
         const int np = g1 - g0;
         for (int e = tid; e < np * W * W; e += blockDim.x) {
