@@ -301,7 +301,10 @@ template <int RADIX, typename C> __device__ __forceinline__ void tw_powers(const
 template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
                                          Store &store) {
-    constexpr int MAXB = (kFftMaxC + RADIX - 1) / RADIX;
+    // values per thread: N * K <= 12288 for the widest workgroups, else
+    // <= NTH * kFftMaxC
+    constexpr int MAXC = NTH >= 512 ? 12288 / NTH : kFftMaxC;
+    constexpr int MAXB = (MAXC + RADIX - 1) / RADIX;
     const int tid = threadIdx.x;
     const int M = N / RADIX;
     const int W = M * K;

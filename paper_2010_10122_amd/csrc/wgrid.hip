@@ -716,8 +716,9 @@ template <typename R, int NTH> struct FftLaunch {
 };
 
 // Row transforms (K = 1, N up to the LDS limit): FP32 256/1024 threads,
-// FP64 256/512.  Column transforms (N * K <= 96 KB of LDS): FP32 256/512,
-// FP64 256.  Each choice keeps a thread at <= kFftMaxC values without spills.
+// FP64 256/512.  Column transforms: FP32 256/1024 (the wide workgroup keeps
+// 16 waves on the CU that its LDS allows), FP64 256.  Each choice keeps a
+// thread at <= kFftMaxC values without spills.
 #define DISPATCH_ROWS(n, EXPR_T)                                       \
     do {                                                               \
         if ((n) <= 256 * kFftMaxC) {                                   \
@@ -734,7 +735,7 @@ template <typename R, int NTH> struct FftLaunch {
             constexpr int NTH = 256;                                   \
             EXPR_T;                                                    \
         } else {                                                       \
-            constexpr int NTH = sizeof(R) == 4 ? 512 : 256;            \
+            constexpr int NTH = sizeof(R) == 4 ? 1024 : 256;           \
             EXPR_T;                                                    \
         }                                                              \
     } while (0)
