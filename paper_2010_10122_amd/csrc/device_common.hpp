@@ -103,36 +103,12 @@ __device__ __forceinline__ VisCoord vis_coord(double u_m, double v_m, double w_m
     return c;
 }
 
-// Kernel values at the alpha cells of one axis from the piecewise
-// polynomials of Sect. 4.2: every cell shares the local variable
-// z = 2 (offset + alpha/2) - 1 in [-1, 1), and cell i uses its own
-// coefficients.  coef is degree-major: coef[d * ALPHA + i].
-template <int ALPHA, typename R>
-__device__ __forceinline__ void kernel_values(double offset, double half, const R *__restrict__ coef,
-                                              int degree, R out[ALPHA]) {
-    const R z = (R)(2.0 * (offset + half) - 1.0);
-#pragma unroll
-    for (int i = 0; i < ALPHA; ++i) out[i] = coef[degree * ALPHA + i];
-    for (int d = degree - 1; d >= 0; --d) {
-#pragma unroll
-        for (int i = 0; i < ALPHA; ++i) out[i] = out[i] * z + coef[d * ALPHA + i];
-    }
-}
-
-// Same, from the precomputed local variable z.
-template <int ALPHA, typename R>
-__device__ __forceinline__ void kernel_values_z(R z, const R *__restrict__ coef, int degree, R out[ALPHA]) {
-#pragma unroll
-    for (int i = 0; i < ALPHA; ++i) out[i] = coef[degree * ALPHA + i];
-    for (int d = degree - 1; d >= 0; --d) {
-#pragma unroll
-        for (int i = 0; i < ALPHA; ++i) out[i] = out[i] * z + coef[d * ALPHA + i];
-    }
-}
-
-// The same for the u, v and w coordinates of one visibility at once: one
-// read of each coefficient row serves all three (3 alpha independent Horner
-// chains per step).
+// Kernel values at the alpha cells of the u, v and w axes of one visibility
+// from the piecewise polynomials of Sect. 4.2: every cell of an axis shares
+// the local variable z = 2 (offset + alpha/2) - 1 in [-1, 1), and cell i
+// uses its own coefficients (coef is degree-major: coef[d * ALPHA + i]).
+// One read of each coefficient row serves all three axes (3 alpha
+// independent Horner chains per step).
 template <int ALPHA, typename R>
 __device__ __forceinline__ void kernel_values_z3(R zu, R zv, R zw, const R *__restrict__ coef, int degree,
                                                  R ku[ALPHA], R kv[ALPHA], R kw[ALPHA]) {

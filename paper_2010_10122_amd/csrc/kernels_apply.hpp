@@ -260,20 +260,25 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
         }
         // per-region lists: wave ballots, then offsets across waves
         unsigned long long bal[ST::NREG];
+        int my_cnt = 0;                                        // lane rg: this wave's count in region rg
 #pragma unroll
         for (int rg = 0; rg < ST::NREG; ++rg) {
             bal[rg] = __ballot((rmask >> rg) & 1);
-            if (lane == 0) s_cnt[rg * 4 + wave] = (int)__popcll(bal[rg]);
+            my_cnt = lane == rg ? (int)__popcll(bal[rg]) : my_cnt;
         }
+        if (lane < ST::NREG) s_cnt[lane * 4 + wave] = my_cnt;
         __syncthreads();
+        // lane rg: where this wave's entries of region rg start
+        int my_off = 0;
+        if (lane < ST::NREG) {
+            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + lane * 4);
+            my_off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
+        }
         const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int rg = 0; rg < ST::NREG; ++rg) {
-            if ((rmask >> rg) & 1) {
-                const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
-                const int off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
-                s_list[rg * ST::LST + off + (int)__popcll(bal[rg] & lt)] = (uint16_t)tid;
-            }
+            const int off = __builtin_amdgcn_readlane(my_off, rg);
+            if ((rmask >> rg) & 1) s_list[rg * ST::LST + off + (int)__popcll(bal[rg] & lt)] = (uint16_t)tid;
         }
         // pad every list with the zero slot up to a multiple of 4, plus the
         // 4 entries read ahead by the last step
