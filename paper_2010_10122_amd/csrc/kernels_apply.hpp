@@ -62,6 +62,18 @@ template <typename R> struct VisArgs {
 // cross-lane shuffles.  Every LDS access in phase 2 is a read, so waves never
 // wait on each other and need no atomics.
 // ---------------------------------------------------------------------------
+// Per-visibility record of the gridder's phase 2: weighted value and the
+// row bases of its padded u and v kernel rows (one 16-byte read in FP32).
+template <typename R> struct GridRec {
+    Cx<R> d;
+    int2 bs;
+};
+
+// Highest polynomial degree the planner picks for a support of ALPHA cells
+// (Sect. 4.2 uses ALPHA + 3); the kernels stage the coefficient table in LDS.
+template <int ALPHA> constexpr int kMaxDegree = ALPHA + 3;
+template <typename R, int ALPHA> constexpr size_t kCoefBytes = (size_t)(kMaxDegree<ALPHA> + 1) * ALPHA * sizeof(R);
+
 template <typename R, int ALPHA, int PS> struct GridStage {
     static constexpr int CH = 256;                 // visibilities per chunk (one per phase-1 thread)
     static constexpr int S = CH + 1;               // + one zero slot used as padding
@@ -72,12 +84,34 @@ template <typename R, int ALPHA, int PS> struct GridStage {
     static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
     static constexpr size_t off_kv = al((size_t)NKP * sizeof(R));
     static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(R));
-    static constexpr size_t off_d = al(off_kw + (size_t)S * PS * sizeof(R));
-    static constexpr size_t off_base = al(off_d + (size_t)S * sizeof(Cx<R>));
-    static constexpr size_t off_list = al(off_base + (size_t)S * sizeof(int2));
+    static constexpr size_t off_rec = al(off_kw + (size_t)S * PS * sizeof(R));
+    static constexpr size_t off_list = al(off_rec + (size_t)S * sizeof(GridRec<R>));
     static constexpr size_t off_cnt = al(off_list + (size_t)NREG * LST * sizeof(uint16_t));
-    static constexpr size_t bytes = off_cnt + (size_t)NREG * 4 * sizeof(int);
+    static constexpr size_t off_coef = al(off_cnt + (size_t)NREG * 4 * sizeof(int));
+    static constexpr size_t bytes = off_coef + kCoefBytes<R, ALPHA>;
 };
+
+// The w weights of one visibility on the batch's plane slots: slot rr holds
+// kernel cell rr + sh (zero outside [0, ALPHA)), for a shift sh in
+// [1 - PS, ALPHA - 1].  A barrel shifter over a zero-padded copy: one select
+// per element and set bit of the shift, all register indices static.
+template <typename R, int ALPHA, int PS>
+__device__ __forceinline__ void rotate_w(const R kw[ALPHA], int sh, R out[PS]) {
+    constexpr int NE = ALPHA + 2 * (PS - 1);
+    R e[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) e[k] = (k >= PS - 1 && k < PS - 1 + ALPHA) ? kw[k - (PS - 1)] : (R)0;
+    const int o = sh + PS - 1;                     // in [0, NE - PS]
+#pragma unroll
+    for (int b = 16; b >= 1; b >>= 1) {
+        if (b > NE - PS) continue;
+        const bool take = (o & b) != 0;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) e[k] = take ? (k + b < NE ? e[k + b] : (R)0) : e[k];
+    }
+#pragma unroll
+    for (int rr = 0; rr < PS; ++rr) out[rr] = e[rr];
+}
 
 // Swaps across lane rows (gfx950 v_permlane32_swap / v_permlane16_swap):
 // swap32 exchanges lanes 32..63 of x with lanes 0..31 of y; swap16 exchanges
@@ -149,10 +183,10 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
     R *s_ku = reinterpret_cast<R *>(smem_raw);                         // [S][KP] + tail
     R *s_kv = reinterpret_cast<R *>(smem_raw + ST::off_kv);            // [S][KP] + tail
     R *s_kw = reinterpret_cast<R *>(smem_raw + ST::off_kw);            // [S][PS]
-    C *s_d = reinterpret_cast<C *>(smem_raw + ST::off_d);              // [S]
-    int2 *s_base = reinterpret_cast<int2 *>(smem_raw + ST::off_base);  // [S] row bases into s_ku / s_kv
+    GridRec<R> *s_rec = reinterpret_cast<GridRec<R> *>(smem_raw + ST::off_rec);   // [S]
     uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);   // [16][LST]
     int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);      // [16 regions][4 waves]
+    R *s_coef = reinterpret_cast<R *>(smem_raw + ST::off_coef);        // [degree + 1][ALPHA]
 
     const Geom &g = a.g;
     int4 item;                                                 // (tile, first, count, slot or -1)
@@ -187,9 +221,12 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
     const uint32_t last = min(total, first + (uint32_t)item.z);
     // the padding slot contributes nothing: zero value, zero kernel rows
     if (tid == 0) {
-        s_d[CH] = cmake<C>((R)0, (R)0);
-        s_base[CH] = make_int2(CH * KP, CH * KP);
+        GridRec<R> z;
+        z.d = cmake<C>((R)0, (R)0);
+        z.bs = make_int2(CH * KP, CH * KP);
+        s_rec[CH] = z;
     }
+    for (int e = tid; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
     if (tid < KP + 16) {
         s_ku[CH * KP + tid] = (R)0;
         s_kv[CH * KP + tid] = (R)0;
@@ -201,10 +238,12 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 #pragma unroll
         for (int r = 0; r < PS; ++r) acc_re[q][r] = acc_im[q][r] = (R)0;
 
+    __syncthreads();                                           // coefficient table staged
+
     for (uint32_t base = first; base < last; base += CH) {
         // ---- phase 1: one thread per visibility -------------------------
         const uint32_t pos = base + tid;
-        int rmask = 0;
+        int bm = 0, cm = 0;                                    // tile rows / columns of 4 cells met
         if (pos < last) {
             // sorted position: select chain (no dynamic register indexing)
             uint32_t s = b_s0[0] + pos;
@@ -217,20 +256,18 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             int lb0 = iv - B * kTileCells;
             if (la0 > g.nu / 2) la0 -= g.nu;
             if (lb0 > g.nv / 2) lb0 -= g.nv;
-            s_base[tid] = make_int2(tid * KP - la0 + 3, tid * KP - lb0 + 3);
-            int bm = 0, cm = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (la0 <= 4 * q + 3 && la0 + ALPHA > 4 * q) bm |= 1 << q;
                 if (lb0 <= 4 * q + 3 && lb0 + ALPHA > 4 * q) cm |= 1 << q;
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if ((bm >> q) & 1) rmask |= cm << (4 * q);
-            s_d[tid] = a.vsorted[s];
+            GridRec<R> rec;
+            rec.d = a.vsorted[s];
+            rec.bs = make_int2(tid * KP - la0 + 3, tid * KP - lb0 + 3);
+            s_rec[tid] = rec;
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, a.coef, a.degree, ku, kv, kw);
+            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
             R *pu = s_ku + tid * KP;
             R *pv = s_kv + tid * KP;
 #pragma unroll
@@ -243,30 +280,37 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
                 pu[3 + i] = ku[i];
                 pv[3 + i] = kv[i];
             }
-            // plane slot rr holds plane j_lo + rr; kernel index j - iw
+            // plane slot rr holds plane j_lo + rr, kernel cell j_lo + rr - iw
+            // (slots past the last plane of the batch are never stored)
             if (g.do_w) {
-                const int sh = j_lo - iw;                      // kernel index of slot 0
+                R ws[PS];
+                rotate_w<R, ALPHA, PS>(kw, j_lo - iw, ws);
 #pragma unroll
-                for (int rr = 0; rr < PS; ++rr) {
-                    R wv = (R)0;
-#pragma unroll
-                    for (int i = 0; i < ALPHA; ++i) wv = (i == rr + sh && j_lo + rr < j_hi) ? kw[i] : wv;
-                    s_kw[tid * PS + rr] = wv;
-                }
+                for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = ws[rr];
             } else {
 #pragma unroll
                 for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = (R)(rr == 0);
             }
         }
-        // per-region lists: wave ballots, then offsets across waves
-        unsigned long long bal[ST::NREG];
-        int my_cnt = 0;                                        // lane rg: this wave's count in region rg
+        // per-region lists.  The regions a footprint meets form the product
+        // of its row and column masks, so the wave ballots of the 16 regions
+        // are products of 4 row and 4 column ballots; counts stay scalar.
+        unsigned long long balr[4], balc[4];
 #pragma unroll
-        for (int rg = 0; rg < ST::NREG; ++rg) {
-            bal[rg] = __ballot((rmask >> rg) & 1);
-            my_cnt = lane == rg ? (int)__popcll(bal[rg]) : my_cnt;
+        for (int q = 0; q < 4; ++q) {
+            balr[q] = __ballot((bm >> q) & 1);
+            balc[q] = __ballot((cm >> q) & 1);
         }
-        if (lane < ST::NREG) s_cnt[lane * 4 + wave] = my_cnt;
+        if (lane < ST::NREG) {                                 // lane rg: this wave's count in region rg
+            const int qr = lane >> 2, qc = lane & 3;
+            unsigned long long br = balr[0], bc = balc[0];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                br = qr == q ? balr[q] : br;
+                bc = qc == q ? balc[q] : bc;
+            }
+            s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
+        }
         __syncthreads();
         // lane rg: where this wave's entries of region rg start
         int my_off = 0;
@@ -274,11 +318,14 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + lane * 4);
             my_off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
         }
-        const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int rg = 0; rg < ST::NREG; ++rg) {
+            const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
             const int off = __builtin_amdgcn_readlane(my_off, rg);
-            if ((rmask >> rg) & 1) s_list[rg * ST::LST + off + (int)__popcll(bal[rg] & lt)] = (uint16_t)tid;
+            // rank among this wave's members + the wave's offset
+            const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
+            if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[rg * ST::LST + at] = (uint16_t)tid;
         }
         // pad every list with the zero slot up to a multiple of 4, plus the
         // 4 entries read ahead by the last step
@@ -299,19 +346,19 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             const int n4 = __builtin_amdgcn_readfirstlane((c4.x + c4.y + c4.z + c4.w + 3) & ~3);
             const uint16_t *lst = s_list + rg * ST::LST + grp;
             const int col = 4 * q + cc;
-            int v = lst[0];
-            int2 bs = s_base[v];
+            unsigned v = lst[0];
+            GridRec<R> rc = s_rec[v];
+#pragma unroll 2
             for (int j = 0; j < n4; j += 4) {
-                const R ku = s_ku[bs.x + row], kv = s_kv[bs.y + col];
-                const C d = s_d[v];
+                const R ku = s_ku[rc.bs.x + row], kv = s_kv[rc.bs.y + col];
                 const R *kwp = s_kw + v * PS;
                 R kw[PS];
 #pragma unroll
                 for (int r = 0; r < PS; ++r) kw[r] = kwp[r];
-                int vn = lst[j + 4];
-                int2 bsn = s_base[vn];
+                unsigned vn = lst[j + 4];
+                GridRec<R> rn = s_rec[vn];
                 const R wuv = ku * kv;
-                const R fr = d.x * wuv, fi = d.y * wuv;
+                const R fr = rc.d.x * wuv, fi = rc.d.y * wuv;
 #pragma unroll
                 for (int r = 0; r < PS; ++r) {
                     acc_re[q][r] += fr * kw[r];
@@ -319,9 +366,9 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
                 }
                 // keep the read-ahead values in registers (not re-read from
                 // LDS at the top of the next step)
-                asm volatile("" : "+v"(vn), "+v"(bsn.x), "+v"(bsn.y));
+                asm volatile("" : "+v"(vn), "+v"(rn.bs.x), "+v"(rn.bs.y), "+v"(rn.d.x), "+v"(rn.d.y));
                 v = vn;
-                bs = bsn;
+                rc = rn;
             }
         }
         __syncthreads();
@@ -396,6 +443,7 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
     constexpr int W = kTileCells + ALPHA - 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *st = reinterpret_cast<C *>(smem_raw);                  // [PD][W][W]
+    R *s_coef = reinterpret_cast<R *>(smem_raw + (((size_t)PD * W * W * sizeof(C) + 15) & ~(size_t)15));
     const Geom &g = a.g;
     int4 item;                                                 // (tile, first position, count, -)
     if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
@@ -412,6 +460,7 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
     }
     if (s0 >= s1) return;
     const int tid = threadIdx.x;
+    for (int e = tid; e < (a.degree + 1) * ALPHA; e += blockDim.x) s_coef[e] = a.coef[e];
     const int j_lo = J * a.P;
     int j_hi = min(j_lo + a.P, g.nw);
     int j_first = j_lo;
@@ -447,7 +496,7 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
             if (jw0 >= jw1) continue;
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, a.coef, a.degree, ku, kv, kw);
+            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
             if (!g.do_w) {
 #pragma unroll
                 for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);

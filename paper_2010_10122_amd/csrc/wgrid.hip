@@ -460,6 +460,7 @@ int plan_build(wg_plan *p) {
     p->mu = row->mu;
     p->eps_k = row->eps;
     p->degree = choose_degree(p->alpha, p->beta, p->mu, p->eps_k, d.precision);
+    if (p->degree > p->alpha + 3) return WG_EUNSUPPORTED;   // the kernels' LDS table holds alpha + 4 rows
 
     // geometry (Sect. 2)
     Geom &g = p->g;
@@ -667,7 +668,7 @@ template <typename R, int ALPHA> struct Launch {
         const uint32_t ne = p->xd_off[J + 1] - p->xd_off[J];
         const int W = kTileCells + ALPHA - 1;
         const int pd = std::max(1, std::min(p->P, (int)(72 * 1024 / ((size_t)W * W * sizeof(Cx<R>)))));
-        const size_t lds = (size_t)pd * W * W * sizeof(Cx<R>);
+        const size_t lds = (((size_t)pd * W * W * sizeof(Cx<R>) + 15) & ~(size_t)15) + kCoefBytes<R, ALPHA>;
         hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J, pd,
                            p->xd + p->xd_off[J], (int)ne, kDegridItemCap, G, vacc);
     }
