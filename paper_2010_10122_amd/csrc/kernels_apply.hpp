@@ -173,6 +173,110 @@ __device__ __forceinline__ bool work_item(const int4 *__restrict__ extra, int n_
     return true;
 }
 
+// The four bins whose visibilities can reach tile (A, B) in batch J (the
+// tile's own and those of the three neighbours up/left), as one
+// concatenated list of sorted positions.
+struct TileBins {
+    uint32_t s0[4], end[4];      // first sorted position, running end of the concatenation
+    uint32_t total;
+};
+template <typename R>
+__device__ __forceinline__ TileBins tile_bins(const VisArgs<R> &a, int J, int A, int B) {
+    const Geom &g = a.g;
+    TileBins tb;
+    tb.total = 0;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        int tu = A - 1 + (nb >> 1);
+        int tv = B - 1 + (nb & 1);
+        if (tu < 0) tu += g.ntu;
+        if (tv < 0) tv += g.ntv;
+        const int64_t bin = (int64_t)tu * g.ntv + tv;
+        const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
+        const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
+        tb.s0[nb] = s0;
+        tb.total += s1 > s0 ? s1 - s0 : 0u;
+        tb.end[nb] = tb.total;
+    }
+    return tb;
+}
+// sorted position of entry pos of the concatenation (a select chain, no
+// dynamic register indexing)
+__device__ __forceinline__ uint32_t tile_bins_pos(const TileBins &tb, uint32_t pos) {
+    uint32_t s = tb.s0[0] + pos;
+    s = pos >= tb.end[0] ? tb.s0[1] + (pos - tb.end[0]) : s;
+    s = pos >= tb.end[1] ? tb.s0[2] + (pos - tb.end[1]) : s;
+    s = pos >= tb.end[2] ? tb.s0[3] + (pos - tb.end[2]) : s;
+    return s;
+}
+// Tile-relative first cell of a footprint and the masks of the tile's rows
+// (bm) and columns (cm) of 4 cells it meets.
+template <int ALPHA>
+__device__ __forceinline__ void footprint_masks(int2 an, int A, int B, const Geom &g, int &la0, int &lb0, int &bm,
+                                                int &cm) {
+    const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff;
+    la0 = iu - A * kTileCells;
+    lb0 = iv - B * kTileCells;
+    if (la0 > g.nu / 2) la0 -= g.nu;
+    if (lb0 > g.nv / 2) lb0 -= g.nv;
+    bm = cm = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (la0 <= 4 * q + 3 && la0 + ALPHA > 4 * q) bm |= 1 << q;
+        if (lb0 <= 4 * q + 3 && lb0 + ALPHA > 4 * q) cm |= 1 << q;
+    }
+}
+// Per-region lists of a chunk: region rg = (tile rows 4 (rg >> 2) ..,
+// columns 4 (rg & 3) ..) lists, in thread order, the chunk slots whose
+// footprint meets it.  The regions a footprint meets form the product of
+// its row and column masks, so the wave ballots of the 16 regions are
+// products of 4 row and 4 column ballots.  Every list is padded with the
+// zero slot (index CH) to a multiple of 4 plus the 4 entries read ahead by
+// the last step.  Ends with a barrier; s_cnt[rg * 4 + wave] holds the counts.
+template <int CH, int LST>
+__device__ __forceinline__ void build_region_lists(int bm, int cm, int tid, int lane, int wave, int *s_cnt,
+                                                   uint16_t *s_list) {
+    unsigned long long balr[4], balc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        balr[q] = __ballot((bm >> q) & 1);
+        balc[q] = __ballot((cm >> q) & 1);
+    }
+    if (lane < 16) {                                           // lane rg: this wave's count in region rg
+        const int qr = lane >> 2, qc = lane & 3;
+        unsigned long long br = balr[0], bc = balc[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            br = qr == q ? balr[q] : br;
+            bc = qc == q ? balc[q] : bc;
+        }
+        s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
+    }
+    __syncthreads();
+    // lane rg: where this wave's entries of region rg start
+    int my_off = 0;
+    if (lane < 16) {
+        const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + lane * 4);
+        my_off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
+    }
+#pragma unroll
+    for (int rg = 0; rg < 16; ++rg) {
+        const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
+        const int off = __builtin_amdgcn_readlane(my_off, rg);
+        // rank among this wave's members + the wave's offset
+        const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
+        if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[rg * LST + at] = (uint16_t)tid;
+    }
+    if (tid < 16 * 8) {
+        const int rg = tid >> 3, k = tid & 7;
+        const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
+        const int n = c4.x + c4.y + c4.z + c4.w;
+        if (n + k < ((n + 3) & ~3) + 4) s_list[rg * LST + n + k] = (uint16_t)CH;
+    }
+    __syncthreads();
+}
+
 template <typename R, int ALPHA, int PS>
 __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra,
                                               int cap, Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
@@ -199,26 +303,10 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
     const int cc = cell & 3;                                   // column within a region
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
-    // the four contributing bins as one concatenated list
-    uint32_t b_s0[4], b_end[4];
-    uint32_t total = 0;
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        int tu = A - 1 + (nb >> 1);
-        int tv = B - 1 + (nb & 1);
-        if (tu < 0) tu += g.ntu;
-        if (tv < 0) tv += g.ntv;
-        const int64_t bin = (int64_t)tu * g.ntv + tv;
-        const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
-        const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
-        const uint32_t n = s1 > s0 ? s1 - s0 : 0u;
-        b_s0[nb] = s0;
-        total += n;
-        b_end[nb] = total;
-    }
+    const TileBins tb = tile_bins(a, J, A, B);
     // this item's share of the concatenated list
     const uint32_t first = (uint32_t)item.y;
-    const uint32_t last = min(total, first + (uint32_t)item.z);
+    const uint32_t last = min(tb.total, first + (uint32_t)item.z);
     // the padding slot contributes nothing: zero value, zero kernel rows
     if (tid == 0) {
         GridRec<R> z;
@@ -237,7 +325,6 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int r = 0; r < PS; ++r) acc_re[q][r] = acc_im[q][r] = (R)0;
-
     __syncthreads();                                           // coefficient table staged
 
     for (uint32_t base = first; base < last; base += CH) {
@@ -245,22 +332,11 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
         const uint32_t pos = base + tid;
         int bm = 0, cm = 0;                                    // tile rows / columns of 4 cells met
         if (pos < last) {
-            // sorted position: select chain (no dynamic register indexing)
-            uint32_t s = b_s0[0] + pos;
-            s = pos >= b_end[0] ? b_s0[1] + (pos - b_end[0]) : s;
-            s = pos >= b_end[1] ? b_s0[2] + (pos - b_end[1]) : s;
-            s = pos >= b_end[2] ? b_s0[3] + (pos - b_end[2]) : s;
+            const uint32_t s = tile_bins_pos(tb, pos);
             const int2 an = a.anc[s];
-            const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
-            int la0 = iu - A * kTileCells;
-            int lb0 = iv - B * kTileCells;
-            if (la0 > g.nu / 2) la0 -= g.nu;
-            if (lb0 > g.nv / 2) lb0 -= g.nv;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (la0 <= 4 * q + 3 && la0 + ALPHA > 4 * q) bm |= 1 << q;
-                if (lb0 <= 4 * q + 3 && lb0 + ALPHA > 4 * q) cm |= 1 << q;
-            }
+            const int iw = an.y & 0x7fffffff;
+            int la0, lb0;
+            footprint_masks<ALPHA>(an, A, B, g, la0, lb0, bm, cm);
             GridRec<R> rec;
             rec.d = a.vsorted[s];
             rec.bs = make_int2(tid * KP - la0 + 3, tid * KP - lb0 + 3);
@@ -292,50 +368,7 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
                 for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = (R)(rr == 0);
             }
         }
-        // per-region lists.  The regions a footprint meets form the product
-        // of its row and column masks, so the wave ballots of the 16 regions
-        // are products of 4 row and 4 column ballots; counts stay scalar.
-        unsigned long long balr[4], balc[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            balr[q] = __ballot((bm >> q) & 1);
-            balc[q] = __ballot((cm >> q) & 1);
-        }
-        if (lane < ST::NREG) {                                 // lane rg: this wave's count in region rg
-            const int qr = lane >> 2, qc = lane & 3;
-            unsigned long long br = balr[0], bc = balc[0];
-#pragma unroll
-            for (int q = 1; q < 4; ++q) {
-                br = qr == q ? balr[q] : br;
-                bc = qc == q ? balc[q] : bc;
-            }
-            s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
-        }
-        __syncthreads();
-        // lane rg: where this wave's entries of region rg start
-        int my_off = 0;
-        if (lane < ST::NREG) {
-            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + lane * 4);
-            my_off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
-        }
-#pragma unroll
-        for (int rg = 0; rg < ST::NREG; ++rg) {
-            const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
-            const int off = __builtin_amdgcn_readlane(my_off, rg);
-            // rank among this wave's members + the wave's offset
-            const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
-            if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[rg * ST::LST + at] = (uint16_t)tid;
-        }
-        // pad every list with the zero slot up to a multiple of 4, plus the
-        // 4 entries read ahead by the last step
-        if (tid < ST::NREG * 8) {
-            const int rg = tid >> 3, k = tid & 7;
-            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
-            const int n = c4.x + c4.y + c4.z + c4.w;
-            if (n + k < ((n + 3) & ~3) + 4) s_list[rg * ST::LST + n + k] = (uint16_t)CH;
-        }
-        __syncthreads();
+        build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
         // ---- phase 2: this wave's four regions, four visibilities a step --
         // (software-pipelined: the next step's list entry and row bases are
         // read while the current step accumulates)
@@ -348,7 +381,6 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             const int col = 4 * q + cc;
             unsigned v = lst[0];
             GridRec<R> rc = s_rec[v];
-#pragma unroll 2
             for (int j = 0; j < n4; j += 4) {
                 const R ku = s_ku[rc.bs.x + row], kv = s_kv[rc.bs.y + col];
                 const R *kwp = s_kw + v * PS;
@@ -398,6 +430,166 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 #pragma unroll
     for (int r = 0; r < PS; ++r)
         if (r < np) dst[r * pstride] = cmake<C>(tot_re[r], tot_im[r]);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 gridder on the matrix cores.  Same tiles, items, chunks and region
+// lists as k_grid; phase 2 is a matrix product per region.  For the four
+// visibilities k of a step and the 16 cells m of a region,
+//     D[n][m] += sum_k  dk_k[n] * (ku_k[row m] kv_k[col m]),
+// where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility times
+// its w weight on plane slot n / 2 (computed once per visibility in phase
+// 1).  That is one v_mfma_f32_16x16x4_f32: lane l supplies A[n = l % 16][k]
+// = dk and B[k][m = l % 16] = the uv weight of the cell, k = l / 16, and
+// ends holding D[4 (l / 16) + i][l % 16], i.e. cell l % 16 of planes
+// 2 (l / 16) and 2 (l / 16) + 1.  The u and v kernel rows sit back to back
+// with three zeros between them (the zeros after a row are the next row's
+// leading ones), so every cell of a region the footprint meets indexes a
+// kernel value or a zero.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int ALPHA> struct GridStageMx {
+    static constexpr int CH = 256;                 // visibilities per chunk
+    static constexpr int S = CH + 1;               // + the zero padding slot
+    static constexpr int KP = ALPHA + 3;           // kernel row + the gap before the next one
+    static constexpr int NKP = (S + 1) * KP + 16;  // rows 0..CH (row CH all zero) + zero tail
+    static constexpr int ND = 16;                  // dk values per visibility
+    static constexpr int LST = CH + 8;
+    static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
+    static constexpr size_t off_kv = al((size_t)NKP * sizeof(float));
+    static constexpr size_t off_dk = al(off_kv + (size_t)NKP * sizeof(float));
+    static constexpr size_t off_bs = al(off_dk + (size_t)S * ND * sizeof(float));
+    static constexpr size_t off_list = al(off_bs + (size_t)S * sizeof(int2));
+    static constexpr size_t off_cnt = al(off_list + (size_t)16 * LST * sizeof(uint16_t));
+    static constexpr size_t off_coef = al(off_cnt + (size_t)16 * 4 * sizeof(int));
+    static constexpr size_t bytes = off_coef + kCoefBytes<float, ALPHA>;
+};
+
+template <int ALPHA, int PS>
+__global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra,
+                                                 int n_extra, int cap, float2 *__restrict__ G,
+                                                 float2 *__restrict__ part) {
+    using ST = GridStageMx<ALPHA>;
+    constexpr int CH = ST::CH, KP = ST::KP, ND = ST::ND;
+    static_assert(2 * PS <= ND, "two dk values per plane slot");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *s_ku = reinterpret_cast<float *>(smem_raw);                 // row v at 3 + v KP
+    float *s_kv = reinterpret_cast<float *>(smem_raw + ST::off_kv);
+    float *s_dk = reinterpret_cast<float *>(smem_raw + ST::off_dk);    // [S][ND]
+    int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);      // [S] row bases into s_ku / s_kv
+    uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);
+    int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);
+    float *s_coef = reinterpret_cast<float *>(smem_raw + ST::off_coef);
+
+    const Geom &g = a.g;
+    int4 item;
+    if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
+    const int tile = item.x;
+    const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kv_of = lane >> 4, m = lane & 15;                // visibility of the step, region cell
+    const int row = 4 * wave + (m >> 2);                       // this lane's tile row
+    const int cc = m & 3;
+    const int j_lo = J * a.P;
+    const int j_hi = min(j_lo + a.P, g.nw);
+    const TileBins tb = tile_bins(a, J, A, B);
+    const uint32_t first = (uint32_t)item.y;
+    const uint32_t last = min(tb.total, first + (uint32_t)item.z);
+    // zero kernel rows and gaps (rows only ever overwrite their own ALPHA
+    // values), the zero slot's dk and row bases, the coefficient table
+    for (int e = tid; e < ST::NKP; e += CH) {
+        s_ku[e] = 0.f;
+        s_kv[e] = 0.f;
+    }
+    if (tid < ND) s_dk[CH * ND + tid] = 0.f;
+    if (tid == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
+    for (int e = tid; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
+    f32x4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+
+    for (uint32_t base = first; base < last; base += CH) {
+        // ---- phase 1: one thread per visibility -------------------------
+        const uint32_t pos = base + tid;
+        int bm = 0, cm = 0;
+        if (pos < last) {
+            const uint32_t s = tile_bins_pos(tb, pos);
+            const int2 an = a.anc[s];
+            const int iw = an.y & 0x7fffffff;
+            int la0, lb0;
+            footprint_masks<ALPHA>(an, A, B, g, la0, lb0, bm, cm);
+            s_bs[tid] = make_int2(3 + tid * KP - la0, 3 + tid * KP - lb0);
+            const float2 d = a.vsorted[s];
+            const float zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
+            float ku[ALPHA], kv[ALPHA], kw[ALPHA];
+            kernel_values_z3<ALPHA, float>(zu, zv, g.do_w ? zw : 0.f, s_coef, a.degree, ku, kv, kw);
+            float *pu = s_ku + 3 + tid * KP;
+            float *pv = s_kv + 3 + tid * KP;
+#pragma unroll
+            for (int i = 0; i < ALPHA; ++i) {
+                pu[i] = ku[i];
+                pv[i] = kv[i];
+            }
+            // plane slot rr holds plane j_lo + rr, kernel cell j_lo + rr - iw
+            // (slots past the last plane of the batch are never stored)
+            float ws[PS];
+            if (g.do_w) {
+                rotate_w<float, ALPHA, PS>(kw, j_lo - iw, ws);
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? 1.f : 0.f;
+            }
+            float dk[ND];
+#pragma unroll
+            for (int n = 0; n < ND; ++n) dk[n] = n < 2 * PS ? ((n & 1) ? d.y : d.x) * ws[n >> 1] : 0.f;
+            float4 *pd = reinterpret_cast<float4 *>(s_dk + tid * ND);
+#pragma unroll
+            for (int n = 0; n < ND / 4; ++n) pd[n] = make_float4(dk[4 * n], dk[4 * n + 1], dk[4 * n + 2], dk[4 * n + 3]);
+        }
+        build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
+        // ---- phase 2: one matrix product step per four visibilities ------
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rg = wave * 4 + q;
+            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
+            const int n4 = __builtin_amdgcn_readfirstlane((c4.x + c4.y + c4.z + c4.w + 3) & ~3);
+            const uint16_t *lst = s_list + rg * ST::LST + kv_of;
+            const int col = 4 * q + cc;
+            unsigned v = lst[0];
+            int2 bs = s_bs[v];
+            for (int j = 0; j < n4; j += 4) {
+                const float ku = s_ku[bs.x + row], kv = s_kv[bs.y + col];
+                const float av = s_dk[v * ND + m];
+                unsigned vn = lst[j + 4];
+                int2 bsn = s_bs[vn];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ku * kv, acc[q], 0, 0, 0);
+                asm volatile("" : "+v"(vn), "+v"(bsn.x), "+v"(bsn.y));
+                v = vn;
+                bs = bsn;
+            }
+        }
+        __syncthreads();
+    }
+    // lane l holds cell m of region q for planes 2 (l / 16) and 2 (l / 16) + 1
+    const int np = j_hi - j_lo;
+    const int r0 = 2 * kv_of;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int colw = 4 * q + cc;
+        float2 *dst;
+        int64_t pstride;
+        if (item.w < 0) {
+            dst = G + (int64_t)(A * kTileCells + row) * g.nv + (B * kTileCells + colw);
+            pstride = (int64_t)g.nu * g.nv;
+        } else {
+            dst = part + (size_t)item.w * a.P * kTileArea + row * kTileCells + colw;
+            pstride = kTileArea;
+        }
+        if (r0 < np) dst[r0 * pstride] = make_float2(acc[q][0], acc[q][1]);
+        if (r0 + 1 < np) dst[(r0 + 1) * pstride] = make_float2(acc[q][2], acc[q][3]);
+    }
 }
 
 // Adds the partial tiles of split gridder items to the grid planes, in item

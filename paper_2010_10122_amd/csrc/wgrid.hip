@@ -646,15 +646,23 @@ template <typename R, int ALPHA> struct Launch {
         hipLaunchKernelGGL((k_grid<R, ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
+    template <int PS>
+    static void grid_mx(const wg_plan *p, const VisArgs<float> &va, int J, float2 *G, float2 *part,
+                        hipStream_t st) {
+        const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
+        const size_t lds = GridStageMx<ALPHA>::bytes;
+        hipLaunchKernelGGL((k_grid_mx<ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
+                           p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
+    }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        bool done = false;
-        if constexpr (sizeof(R) == 4) {
-            if (p->P > 4) {
-                grid_ps<8>(p, va, J, G, part, st);
-                done = true;
-            }
+        if constexpr (sizeof(R) == 4) {      // FP32: matrix cores
+            if (p->P > 4)
+                grid_mx<8>(p, va, J, G, part, st);
+            else
+                grid_mx<4>(p, va, J, G, part, st);
+        } else {
+            grid_ps<4>(p, va, J, G, part, st);
         }
-        if (!done) grid_ps<4>(p, va, J, G, part, st);
         // partial tiles of split items, added in item order
         const uint32_t nr = p->xr_off[J + 1] - p->xr_off[J];
         if (nr > 0) {
