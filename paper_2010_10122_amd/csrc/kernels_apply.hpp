@@ -496,6 +496,26 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
     const TileBins tb = tile_bins(a, J, A, B);
     const uint32_t first = (uint32_t)item.y;
     const uint32_t last = min(tb.total, first + (uint32_t)item.z);
+    // Inputs of a chunk position (anchor, weighted value, kernel-local
+    // coordinates) are read one chunk ahead: the first chunk's before the
+    // set-up barrier, the next chunk's while the current one accumulates.
+    struct In {
+        int2 an;
+        float2 d;
+        float zu, zv, zw;
+    };
+    auto load_in = [&](uint32_t pos) {
+        In r;
+        const uint32_t s = tile_bins_pos(tb, pos);
+        r.an = a.anc[s];
+        r.d = a.vsorted[s];
+        r.zu = a.z[3 * (size_t)s];
+        r.zv = a.z[3 * (size_t)s + 1];
+        r.zw = a.z[3 * (size_t)s + 2];
+        return r;
+    };
+    In in{};
+    if (first + tid < last) in = load_in(first + tid);
     // zero kernel rows and gaps (rows only ever overwrite their own ALPHA
     // values), the zero slot's dk and row bases, the coefficient table
     for (int e = tid; e < ST::NKP; e += CH) {
@@ -515,16 +535,12 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
         const uint32_t pos = base + tid;
         int bm = 0, cm = 0;
         if (pos < last) {
-            const uint32_t s = tile_bins_pos(tb, pos);
-            const int2 an = a.anc[s];
-            const int iw = an.y & 0x7fffffff;
+            const int iw = in.an.y & 0x7fffffff;
             int la0, lb0;
-            footprint_masks<ALPHA>(an, A, B, g, la0, lb0, bm, cm);
+            footprint_masks<ALPHA>(in.an, A, B, g, la0, lb0, bm, cm);
             s_bs[tid] = make_int2(3 + tid * KP - la0, 3 + tid * KP - lb0);
-            const float2 d = a.vsorted[s];
-            const float zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             float ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, float>(zu, zv, g.do_w ? zw : 0.f, s_coef, a.degree, ku, kv, kw);
+            kernel_values_z3<ALPHA, float>(in.zu, in.zv, g.do_w ? in.zw : 0.f, s_coef, a.degree, ku, kv, kw);
             float *pu = s_ku + 3 + tid * KP;
             float *pv = s_kv + 3 + tid * KP;
 #pragma unroll
@@ -543,12 +559,13 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
             }
             float dk[ND];
 #pragma unroll
-            for (int n = 0; n < ND; ++n) dk[n] = n < 2 * PS ? ((n & 1) ? d.y : d.x) * ws[n >> 1] : 0.f;
+            for (int n = 0; n < ND; ++n) dk[n] = n < 2 * PS ? ((n & 1) ? in.d.y : in.d.x) * ws[n >> 1] : 0.f;
             float4 *pd = reinterpret_cast<float4 *>(s_dk + tid * ND);
 #pragma unroll
             for (int n = 0; n < ND / 4; ++n) pd[n] = make_float4(dk[4 * n], dk[4 * n + 1], dk[4 * n + 2], dk[4 * n + 3]);
         }
         build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
+        if (base + CH + tid < last) in = load_in(base + CH + tid);
         // ---- phase 2: one matrix product step per four visibilities ------
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
