@@ -796,6 +796,13 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     // and added to the image once
     R *sum = reinterpret_cast<R *>(buf + (size_t)fft_lds_len(pg.nu) * K);
     const int ne = pg.npix_x * kk;
+    // pixel e of the block is image row pp, column q0 + col (the float
+    // quotient is exact for e < 2^20)
+    const float rk = 1.0f / (float)kk;
+    auto pixel = [&](int e, int &pp, int &col) {
+        pp = (int)(((float)e + 0.5f) * rk);
+        col = e - pp * kk;
+    };
     for (int e = threadIdx.x; e < ne; e += NTH) sum[e] = (R)0;
     for (int p = 0; p < np; ++p) {
         const C *src = T + (int64_t)p * pg.nu * pg.npix_y;
@@ -811,7 +818,8 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
             },
             NoIo{});
         for (int e = threadIdx.x; e < ne; e += NTH) {
-            const int pp = e / kk, col = e - pp * kk;
+            int pp, col;
+            pixel(e, pp, col);
             // image row pp sits at grid row (pp - h) mod N_u
             int ga = pp - h;
             if (ga < 0) ga += pg.nu;
@@ -832,7 +840,8 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
         __syncthreads();
     }
     for (int e = threadIdx.x; e < ne; e += NTH) {
-        const int pp = e / kk, col = e - pp * kk;
+        int pp, col;
+        pixel(e, pp, col);
         acc[(int64_t)pp * pg.npix_y + q0 + col] += sum[e];
     }
 }
