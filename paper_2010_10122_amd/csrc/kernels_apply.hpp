@@ -939,16 +939,19 @@ __global__ void k_fill_zero(T *__restrict__ p, int64_t n) {
 // Degridding output: undo the fold (conjugate), apply the weights and
 // scatter from sorted order to [n_rows][n_chan].
 template <typename R>
-__global__ void k_degrid_finish(const Cx<R> *__restrict__ visacc, const uint32_t *__restrict__ order,
-                                const int2 *__restrict__ anc, const R *__restrict__ wgt, int64_t n_active,
-                                Cx<R> *__restrict__ vis) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t idx = order[s];
-        Cx<R> v = visacc[s];
-        if (anc[s].y < 0) v.y = -v.y;
-        if (wgt) v = cscale(v, wgt[idx]);
-        vis[idx] = v;
+__global__ void k_degrid_finish(const Cx<R> *__restrict__ visacc, const uint32_t *__restrict__ inv,
+                                const R *__restrict__ wgt, int64_t n_total, Cx<R> *__restrict__ vis) {
+    // caller's order out: the writes stay contiguous and the scattered side
+    // is the read (a scattered 8-byte write costs a read-modify-write of a
+    // whole memory sector)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = inv[i];
+        if (e == 0xffffffffu) continue;                    // masked
+        Cx<R> v = visacc[e & 0x7fffffffu];
+        if (e >> 31) v.y = -v.y;                            // folded: conjugate
+        if (wgt) v = cscale(v, wgt[i]);
+        vis[i] = v;
     }
 }
 

@@ -847,8 +847,8 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
             }
             {
                 ProfScope ps(WG_KIND_VIS, st);
-                hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
-                                   0, st, vacc, p->order, p->anc, (const R *)wgt, p->n_active, (C *)out);
+                hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256),
+                                   0, st, vacc, p->inv, (const R *)wgt, p->n_total, (C *)out);
             }
         }
     }
