@@ -298,12 +298,16 @@ template <int RADIX, typename C> __device__ __forceinline__ void tw_powers(const
     }
 }
 
-template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
+// CAP: values per thread the caller guarantees (N * K <= NTH * CAP); 0 for
+// the default, N * K <= 12288 for the widest workgroups, else
+// <= NTH * kFftMaxC.  A smaller CAP keeps fewer registers per pass.
+template <int NTH, int CAP> constexpr int fft_cap() { return CAP > 0 ? CAP : (NTH >= 512 ? 12288 / NTH : kFftMaxC); }
+
+template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, int CAP, typename C, typename Load,
+          typename Store>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
                                          Store &store) {
-    // values per thread: N * K <= 12288 for the widest workgroups, else
-    // <= NTH * kFftMaxC
-    constexpr int MAXC = NTH >= 512 ? 12288 / NTH : kFftMaxC;
+    constexpr int MAXC = fft_cap<NTH, CAP>();
     constexpr int MAXB = (MAXC + RADIX - 1) / RADIX;
     const int tid = threadIdx.x;
     const int M = N / RADIX;
@@ -397,54 +401,54 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
 struct NoIo {
     template <typename... A> __device__ __forceinline__ void operator()(A...) const {}
 };
-template <int RADIX, int DIR, int NTH, bool PF, typename C>
+template <int RADIX, int DIR, int NTH, bool PF, int CAP, typename C>
 __device__ __noinline__ void fft_pass_mid(C *buf, int N, int K, int Ns, const C *__restrict__ tw) {
     NoIo none;
-    fft_pass<RADIX, DIR, NTH, false, false, PF>(buf, N, K, Ns, tw, none, none);
+    fft_pass<RADIX, DIR, NTH, false, false, PF, CAP>(buf, N, K, Ns, tw, none, none);
 }
 
 // one pass of runtime radix r with compile-time role
-template <int DIR, int NTH, bool first, bool last, bool PF, typename C, typename Load, typename Store>
+template <int DIR, int NTH, bool first, bool last, bool PF, int CAP, typename C, typename Load, typename Store>
 __device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, const C *__restrict__ tw,
                                            Load &load, Store &store) {
     if constexpr (!first && !last) {
         switch (r) {
-            case 16: fft_pass_mid<16, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 15: fft_pass_mid<15, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 14: fft_pass_mid<14, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 12: fft_pass_mid<12, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 10: fft_pass_mid<10, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 9: fft_pass_mid<9, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 8: fft_pass_mid<8, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 7: fft_pass_mid<7, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 6: fft_pass_mid<6, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 5: fft_pass_mid<5, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 4: fft_pass_mid<4, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 3: fft_pass_mid<3, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
-            case 2: fft_pass_mid<2, DIR, NTH, PF>(buf, N, K, Ns, tw); break;
+            case 16: fft_pass_mid<16, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 15: fft_pass_mid<15, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 14: fft_pass_mid<14, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 12: fft_pass_mid<12, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 10: fft_pass_mid<10, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 9: fft_pass_mid<9, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 8: fft_pass_mid<8, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 7: fft_pass_mid<7, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 6: fft_pass_mid<6, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 5: fft_pass_mid<5, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 4: fft_pass_mid<4, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 3: fft_pass_mid<3, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
+            case 2: fft_pass_mid<2, DIR, NTH, PF, CAP>(buf, N, K, Ns, tw); break;
             default: break;
         }
         return;
     }
     switch (r) {
-        case 16: fft_pass<16, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 15: fft_pass<15, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 14: fft_pass<14, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 12: fft_pass<12, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 10: fft_pass<10, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 9: fft_pass<9, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 8: fft_pass<8, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 7: fft_pass<7, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 6: fft_pass<6, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 5: fft_pass<5, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 4: fft_pass<4, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 3: fft_pass<3, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
-        case 2: fft_pass<2, DIR, NTH, first, last, PF>(buf, N, K, Ns, tw, load, store); break;
+        case 16: fft_pass<16, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 15: fft_pass<15, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 14: fft_pass<14, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 12: fft_pass<12, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 10: fft_pass<10, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 9: fft_pass<9, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 8: fft_pass<8, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 7: fft_pass<7, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 6: fft_pass<6, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 5: fft_pass<5, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 4: fft_pass<4, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 3: fft_pass<3, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
+        case 2: fft_pass<2, DIR, NTH, first, last, PF, CAP>(buf, N, K, Ns, tw, load, store); break;
         default: break;
     }
 }
 
-// FFT of K interleaved columns of length d.n (d.n * K <= NTH * kFftMaxC).
+// FFT of K interleaved columns of length d.n (d.n * K <= NTH * fft_cap<NTH, CAP>()).
 // Input: with IN_LDS the caller has written element n of column col to
 // buf[fft_lidx(n) * K + col] and synchronised; otherwise the first pass
 // calls load(n, col) -> C.  Output: with OUT_LDS the result is left at
@@ -454,19 +458,20 @@ __device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, 
 // PF: prefetch each pass's twiddles (FP32 only).
 // Passes that only move data between LDS buffers run as functions of their
 // own (fft_pass_mid), which keeps each pass's register allocation apart.
-template <bool IN_LDS, bool OUT_LDS, int DIR, int NTH, bool PF, typename C, typename Load, typename Store>
+template <bool IN_LDS, bool OUT_LDS, int DIR, int NTH, bool PF, int CAP = 0, typename C, typename Load,
+          typename Store>
 __device__ __forceinline__ void lds_fft(C *buf, int K, const FftDesc &d, const C *__restrict__ tw, Load &&load,
                                         Store &&store) {
     // d.npass >= 2: every length here is a multiple of 16 and at least 48
-    if constexpr (IN_LDS) fft_pass_r<DIR, NTH, false, false, PF>(d.radix[0], buf, d.n, K, 1, tw, load, store);
-    else fft_pass_r<DIR, NTH, true, false, PF>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    if constexpr (IN_LDS) fft_pass_r<DIR, NTH, false, false, PF, CAP>(d.radix[0], buf, d.n, K, 1, tw, load, store);
+    else fft_pass_r<DIR, NTH, true, false, PF, CAP>(d.radix[0], buf, d.n, K, 1, tw, load, store);
     int Ns = d.radix[0];
     for (int s = 1; s < d.npass - 1; ++s) {
-        fft_pass_r<DIR, NTH, false, false, PF>(d.radix[s], buf, d.n, K, Ns, tw, load, store);
+        fft_pass_r<DIR, NTH, false, false, PF, CAP>(d.radix[s], buf, d.n, K, Ns, tw, load, store);
         Ns *= d.radix[s];
     }
-    if constexpr (OUT_LDS) fft_pass_r<DIR, NTH, false, false, PF>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
-    else fft_pass_r<DIR, NTH, false, true, PF>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
+    if constexpr (OUT_LDS) fft_pass_r<DIR, NTH, false, false, PF, CAP>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
+    else fft_pass_r<DIR, NTH, false, true, PF, CAP>(d.radix[d.npass - 1], buf, d.n, K, Ns, tw, load, store);
 }
 
 }  // namespace wg

@@ -752,7 +752,7 @@ struct PassGeom {
 // Gridding pass 1: row a of plane p: T[p][a][q] = sum_b G[p][a][b] e^{+2 pi i b q'/N_v}
 // for the npix_y retained q (q' = q - npix_y/2), i.e. the pruned output.
 // The first FFT pass reads the row from HBM, the last writes T.
-template <typename R, int NTH>
+template <typename R, int NTH, int CAP>
 __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, Cx<R> *__restrict__ T,
                                                    PassGeom pg, FftDesc fd, const Cx<R> *__restrict__ tw) {
     using C = Cx<R>;
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, 
     const C *src = G + ((int64_t)p * pg.nu + a) * pg.nv;
     C *dst = T + ((int64_t)p * pg.nu + a) * pg.npix_y;
     const int h = pg.npix_y / 2;
-    lds_fft<false, false, +1, NTH, false>(
+    lds_fft<false, false, +1, NTH, false, CAP>(
         buf, 1, fd, tw, [&](int n, int) { return src[n]; },
         [&](int o, int, C v, int) {
             // output frequency o holds image column q with o = (q - h) mod N_v
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
 // row I~ exp(+2 pi i c_j (n - 1)) (eqs. R1-R2) placed at the wrapped
 // positions of a zero row of length N_v, transformed along v (e^{-2 pi i});
 // the last FFT pass writes T[p][row][b], all N_v columns.
-template <typename R, int NTH>
+template <typename R, int NTH, int CAP>
 __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil, const double *__restrict__ nm1,
                                                      Cx<R> *__restrict__ T, PassGeom pg, int j_lo, int np,
                                                      FftDesc fd, const Cx<R> *__restrict__ tw) {
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
             buf[fft_lidx(b)] = v;
         }
         __syncthreads();
-        lds_fft<true, false, -1, NTH, false>(buf, 1, fd, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
+        lds_fft<true, false, -1, NTH, false, CAP>(buf, 1, fd, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
     }
 }
 

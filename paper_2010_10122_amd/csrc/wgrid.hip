@@ -698,8 +698,9 @@ void launch_vis_kernel(bool gridding, const wg_plan *p, const VisArgs<R> &va, in
 }
 
 template <typename R, int NTH> struct FftLaunch {
+    template <int CAP>
     static void rows_grid(const wg_plan *p, const Cx<R> *G, Cx<R> *T, const PassGeom &pg, int np, hipStream_t st) {
-        hipLaunchKernelGGL((k_rows_grid<R, NTH>), dim3(p->g.nu, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st, G, T,
+        hipLaunchKernelGGL((k_rows_grid<R, NTH, CAP>), dim3(p->g.nu, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st, G, T,
                            pg, p->fft_v, (const Cx<R> *)p->tw_v);
     }
     static void cols_grid(const wg_plan *p, const Cx<R> *T, R *acc, const PassGeom &pg, int j_lo, int np,
@@ -710,9 +711,10 @@ template <typename R, int NTH> struct FftLaunch {
         hipLaunchKernelGGL((k_cols_grid<R, NTH>), dim3(nb), dim3(NTH), lds, st, T,
                            acc, p->nm1, pg, K, j_lo, np, p->fft_u, (const Cx<R> *)p->tw_u);
     }
+    template <int CAP>
     static void rows_degrid(const wg_plan *p, const R *itil, Cx<R> *T, const PassGeom &pg, int j_lo, int np,
                             hipStream_t st) {
-        hipLaunchKernelGGL((k_rows_degrid<R, NTH>), dim3(p->g.npix_x, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
+        hipLaunchKernelGGL((k_rows_degrid<R, NTH, CAP>), dim3(p->g.npix_x, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
                            itil, p->nm1, T, pg, j_lo, np, p->fft_v, (const Cx<R> *)p->tw_v);
     }
     static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
@@ -730,11 +732,14 @@ template <typename R, int NTH> struct FftLaunch {
 // thread at <= kFftMaxC values without spills.
 #define DISPATCH_ROWS(n, EXPR_T)                                       \
     do {                                                               \
-        if ((n) <= 256 * kFftMaxC) {                                   \
-            constexpr int NTH = 256;                                   \
+        if ((n) <= 256 * 12) {                                         \
+            constexpr int NTH = 256, CAP = 12;                         \
+            EXPR_T;                                                    \
+        } else if ((n) <= 256 * kFftMaxC) {                            \
+            constexpr int NTH = 256, CAP = 0;                          \
             EXPR_T;                                                    \
         } else {                                                       \
-            constexpr int NTH = sizeof(R) == 4 ? 1024 : 512;           \
+            constexpr int NTH = sizeof(R) == 4 ? 1024 : 512, CAP = 0;  \
             EXPR_T;                                                    \
         }                                                              \
     } while (0)
@@ -799,7 +804,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 }
                 {
                     ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
-                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_grid(p, G, T, pg, np, st)));
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
                 }
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
@@ -834,7 +839,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 const int np = std::min(p->P, g.nw - j_lo);
                 {
                     ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
-                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::rows_degrid(p, itil, T, pg, j_lo, np, st)));
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
                 }
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
