@@ -680,6 +680,17 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
         j_first = max(j_lo, iw0);
         j_hi = min(j_hi, iw1 + ALPHA);
     }
+    // the first visibility of this thread: its inputs are read before the
+    // staging barrier, so that their latency overlaps the staging loads
+    int2 an_pf = make_int2(0, 0);
+    R zu_pf = 0, zv_pf = 0, zw_pf = 0;
+    if (s0 + tid < s1) {
+        const uint32_t s = s0 + tid;
+        an_pf = a.anc[s];
+        zu_pf = a.z[3 * (size_t)s];
+        zv_pf = a.z[3 * (size_t)s + 1];
+        zw_pf = a.z[3 * (size_t)s + 2];
+    }
     // planes are staged PD at a time (tile + halo of PD planes in LDS)
     for (int g0 = j_first; g0 < j_hi; g0 += PD) {
         const int g1 = min(g0 + PD, j_hi);
@@ -695,7 +706,19 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
         }
         __syncthreads();
         for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
-            const int2 an = a.anc[s];
+            int2 an;
+            R zu, zv, zw;
+            if (s == s0 + tid) {
+                an = an_pf;
+                zu = zu_pf;
+                zv = zv_pf;
+                zw = zw_pf;
+            } else {
+                an = a.anc[s];
+                zu = a.z[3 * (size_t)s];
+                zv = a.z[3 * (size_t)s + 1];
+                zw = a.z[3 * (size_t)s + 2];
+            }
             const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
             const int la0 = iu - A * kTileCells;   // in [0, 16) by the index
             const int lb0 = iv - B * kTileCells;
@@ -703,7 +726,8 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
             const int jw0 = g.do_w ? max(iw, g0) : g0;
             const int jw1 = g.do_w ? min(iw + ALPHA, g1) : g1;
             if (jw0 >= jw1) continue;
-            const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
+            // the running sum, read now and written back at the end
+            const C old = visacc[s];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
             kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
             if (!g.do_w) {
@@ -732,7 +756,6 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
                 sre += kw[jw] * pre;
                 sim += kw[jw] * pim;
             }
-            C old = visacc[s];
             visacc[s] = cmake<C>(old.x + sre, old.y + sim);
         }
         __syncthreads();
