@@ -915,7 +915,7 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
 // Degridding pass B: K grid columns b of plane p: the npix_x rows of T are
 // placed at wrapped u positions of a zero column of length N_u and
 // transformed along u (e^{-2 pi i}); output G[p][a][b] for all a.
-template <typename R, int NTH>
+template <typename R, int NTH, int CAP>
 __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T, Cx<R> *__restrict__ G,
                                                      PassGeom pg, int K, FftDesc fd,
                                                      const Cx<R> *__restrict__ tw) {
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
     const int h = pg.npix_x / 2;
     const C *src = T + (int64_t)p * pg.npix_x * pg.nv;
     C *dst = G + (int64_t)p * pg.nu * pg.nv;
-    lds_fft<false, false, -1, NTH, true>(
+    lds_fft<false, false, -1, NTH, true, CAP>(
         buf, K, fd, tw,
         [&](int a, int col) {
             // a = (pp - h) mod N_u  <=>  pp = a + h (a < npix_x - h) or a - (N_u - h) (a >= N_u - h)

@@ -215,6 +215,7 @@ struct wg_plan {
     double wmin = 0, wmax = 0, predicted = 0;
     FftDesc fft_u{}, fft_v{};
     int k_cols = 1;     // columns per workgroup in the strided passes
+    int k_cols_d = 1;   // the same for the degridding column pass
     // device arrays
     double *scale = nullptr;           // [n_chan]
     void *coef = nullptr;              // [degree+1][alpha] R
@@ -497,6 +498,7 @@ int plan_build(wg_plan *p) {
     // (the gridding column pass also keeps npix_x * K image sums in LDS)
     while (p->k_cols < 8 && (size_t)(fft_lds_len(g.nu) * sc + d.npix_x * sr) * (2 * p->k_cols) <= 144 * 1024)
         p->k_cols *= 2;
+    p->k_cols_d = p->k_cols;
     // planes per batch: the gridder keeps one register accumulator per plane
     // of the batch and lane, P = alpha (a visibility's alpha planes then meet
     // at most two batches); the degridder stages P planes of tile + halo.
@@ -721,11 +723,12 @@ template <typename R, int NTH> struct FftLaunch {
         hipLaunchKernelGGL((k_rows_degrid<R, NTH, CAP>), dim3(p->g.npix_x, np), dim3(NTH), fft_lds_len(p->g.nv) * sizeof(Cx<R>), st,
                            itil, p->nm1, T, pg, j_lo, np, p->fft_v, (const Cx<R> *)p->tw_v);
     }
+    template <int CAP>
     static void cols_degrid(const wg_plan *p, const Cx<R> *T, Cx<R> *G, const PassGeom &pg, int np,
                             hipStream_t st) {
-        const int K = p->k_cols;
+        const int K = p->k_cols_d;
         const int nb = ((p->g.nv + K - 1) / K + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_cols_degrid<R, NTH>), dim3(nb, np), dim3(NTH), (size_t)fft_lds_len(p->g.nu) * K * sizeof(Cx<R>),
+        hipLaunchKernelGGL((k_cols_degrid<R, NTH, CAP>), dim3(nb, np), dim3(NTH), (size_t)fft_lds_len(p->g.nu) * K * sizeof(Cx<R>),
                            st, T, G, pg, K, p->fft_u, (const Cx<R> *)p->tw_u);
     }
 };
@@ -754,6 +757,17 @@ template <typename R, int NTH> struct FftLaunch {
             EXPR_T;                                                    \
         } else {                                                       \
             constexpr int NTH = sizeof(R) == 4 ? 1024 : 256;           \
+            EXPR_T;                                                    \
+        }                                                              \
+    } while (0)
+
+#define DISPATCH_COLS_D(n, EXPR_T)                                     \
+    do {                                                               \
+        if (sizeof(R) == 8 || (n) <= 256 * kFftMaxC) {                 \
+            constexpr int NTH = 256, CAP = 0;                          \
+            EXPR_T;                                                    \
+        } else {                                                       \
+            constexpr int NTH = sizeof(R) == 4 ? 1024 : 256, CAP = 0;  \
             EXPR_T;                                                    \
         }                                                              \
     } while (0)
@@ -847,7 +861,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 }
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
-                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_degrid(p, T, G, pg, np, st)));
+                    DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
                 }
                 {
                     ProfScope ps(WG_KIND_DEGRID, st);
