@@ -567,24 +567,36 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
         build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
         if (base + CH + tid < last) in = load_in(base + CH + tid);
         // ---- phase 2: one matrix product step per four visibilities ------
+        // Two regions at a time (two independent accumulator chains and
+        // twice the reads in flight); the shorter list reads the zero slot
+        // (its padding entry at index n4) once it is exhausted.
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rg = wave * 4 + q;
-            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
-            const int n4 = __builtin_amdgcn_readfirstlane((c4.x + c4.y + c4.z + c4.w + 3) & ~3);
-            const uint16_t *lst = s_list + rg * ST::LST + kv_of;
-            const int col = 4 * q + cc;
-            unsigned v = lst[0];
-            int2 bs = s_bs[v];
+        for (int qp = 0; qp < 2; ++qp) {
+            const int qa = 2 * qp, qb = 2 * qp + 1;
+            const int rga = wave * 4 + qa, rgb = rga + 1;
+            const int4 ca = *reinterpret_cast<const int4 *>(s_cnt + rga * 4);
+            const int4 cb = *reinterpret_cast<const int4 *>(s_cnt + rgb * 4);
+            const int n4a = __builtin_amdgcn_readfirstlane((ca.x + ca.y + ca.z + ca.w + 3) & ~3);
+            const int n4b = __builtin_amdgcn_readfirstlane((cb.x + cb.y + cb.z + cb.w + 3) & ~3);
+            const int n4 = max(n4a, n4b);
+            const uint16_t *lsta = s_list + rga * ST::LST + kv_of;
+            const uint16_t *lstb = s_list + rgb * ST::LST + kv_of;
+            const int cola = 4 * qa + cc, colb = 4 * qb + cc;
+            unsigned va = lsta[0], vb = lstb[0];
+            int2 bsa = s_bs[va], bsb = s_bs[vb];
             for (int j = 0; j < n4; j += 4) {
-                const float ku = s_ku[bs.x + row], kv = s_kv[bs.y + col];
-                const float av = s_dk[v * ND + m];
-                unsigned vn = lst[j + 4];
-                int2 bsn = s_bs[vn];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ku * kv, acc[q], 0, 0, 0);
-                asm volatile("" : "+v"(vn), "+v"(bsn.x), "+v"(bsn.y));
-                v = vn;
-                bs = bsn;
+                const float kua = s_ku[bsa.x + row], kva = s_kv[bsa.y + cola];
+                const float kub = s_ku[bsb.x + row], kvb = s_kv[bsb.y + colb];
+                const float ava = s_dk[va * ND + m], avb = s_dk[vb * ND + m];
+                unsigned vna = lsta[min(j + 4, n4a)], vnb = lstb[min(j + 4, n4b)];
+                int2 bsna = s_bs[vna], bsnb = s_bs[vnb];
+                acc[qa] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, kua * kva, acc[qa], 0, 0, 0);
+                acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avb, kub * kvb, acc[qb], 0, 0, 0);
+                asm volatile("" : "+v"(vna), "+v"(bsna.x), "+v"(bsna.y), "+v"(vnb), "+v"(bsnb.x), "+v"(bsnb.y));
+                va = vna;
+                bsa = bsna;
+                vb = vnb;
+                bsb = bsnb;
             }
         }
         __syncthreads();
