@@ -11,8 +11,8 @@ resident on the device; plan construction is timed separately (cold).
 value = visibilities / mean time of one operator application, FP32 at
 epsilon = 1e-5; the plain FP64 form at the same epsilon is timed beside it.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the operator runs on
+one GPU (sharding over GPUs is not implemented).
 """
 import argparse
 import json
@@ -334,7 +334,7 @@ def main():
                     help="requests of the serving workload run after the operator timing (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the operator runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 

@@ -38,7 +38,7 @@ extern "C" {
 #define WG_EINVAL       -1   /* invalid argument (see each call)                      */
 #define WG_ENOMEM       -2   /* an allocation failed                                  */
 #define WG_EHIP         -3   /* a HIP runtime call or kernel launch failed            */
-#define WG_EUNSUPPORTED -4   /* valid request outside what this build implements     */
+#define WG_EUNSUPPORTED -4   /* valid request outside what this library implements   */
 
 /* ---- precision --------------------------------------------------------- */
 #define WG_F32 0   /* complex64 visibilities, float32 image (epsilon >= 1e-5)      */
