@@ -277,6 +277,62 @@ __device__ __forceinline__ void build_region_lists(int bm, int cm, int tid, int 
     __syncthreads();
 }
 
+// The same lists packed back to back: region r's list starts at base_r, the
+// sum of the padded lengths of the regions before it, so the capacity is
+// CH times the most regions one footprint meets (not 16 CH).  Returns, in
+// lane r (r = lane mod 16), base_r.  Ends with a barrier.
+template <int CH, int PAD>
+__device__ __forceinline__ int build_region_lists_packed(int bm, int cm, int tid, int lane, int wave, int *s_cnt,
+                                                         uint16_t *s_list) {
+    unsigned long long balr[4], balc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        balr[q] = __ballot((bm >> q) & 1);
+        balc[q] = __ballot((cm >> q) & 1);
+    }
+    if (lane < 16) {
+        const int qr = lane >> 2, qc = lane & 3;
+        unsigned long long br = balr[0], bc = balc[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            br = qr == q ? balr[q] : br;
+            bc = qc == q ? balc[q] : bc;
+        }
+        s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
+    }
+    __syncthreads();
+    // lane r: region r's total, this wave's offset in it, padded length, base
+    const int r = lane & 15;
+    const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + r * 4);
+    const int tot = c4.x + c4.y + c4.z + c4.w;
+    const int woff = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
+    const int len = ((tot + 3) & ~3) + PAD;
+    int base = 0;
+#pragma unroll
+    for (int rr = 0; rr < 15; ++rr) {
+        const int l = __builtin_amdgcn_readlane(len, rr);
+        base += rr < r ? l : 0;
+    }
+    const int start = base + woff;
+#pragma unroll
+    for (int rg = 0; rg < 16; ++rg) {
+        const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
+        const int off = __builtin_amdgcn_readlane(start, rg);
+        const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
+        if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[at] = (uint16_t)tid;
+    }
+    {
+        // thread tid pads region tid / 16 (16 threads a region)
+        const int rg = tid >> 4, k = tid & 15;
+        const int b = __shfl(base, rg), n = __shfl(tot, rg);
+        static_assert(PAD + 3 <= 16, "padding per region");
+        if (n + k < ((n + 3) & ~3) + PAD) s_list[b + n + k] = (uint16_t)CH;
+    }
+    __syncthreads();
+    return base;
+}
+
 template <typename R, int ALPHA, int PS>
 __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra,
                                               int cap, Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
@@ -437,15 +493,18 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 // lists as k_grid; phase 2 is a matrix product per region.  For the four
 // visibilities k of a step and the 16 cells m of a region,
 //     D[n][m] += sum_k  dk_k[n] * (ku_k[row m] kv_k[col m]),
-// where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility times
-// its w weight on plane slot n / 2 (computed once per visibility in phase
-// 1).  That is one v_mfma_f32_16x16x4_f32: lane l supplies A[n = l % 16][k]
-// = dk and B[k][m = l % 16] = the uv weight of the cell, k = l / 16, and
-// ends holding D[4 (l / 16) + i][l % 16], i.e. cell l % 16 of planes
-// 2 (l / 16) and 2 (l / 16) + 1.  The u and v kernel rows sit back to back
-// with three zeros between them (the zeros after a row are the next row's
-// leading ones), so every cell of a region the footprint meets indexes a
-// kernel value or a zero.
+// where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility (its
+// real or imaginary part) times its w weight on plane slot n / 2; phase 1
+// stores the value and the rotated w weights, a lane forms its dk with one
+// product.  That is one v_mfma_f32_16x16x4_f32: lane l supplies
+// A[n = l % 16][k] = dk and B[k][m = l % 16] = the uv weight of the cell,
+// k = l / 16, and ends holding D[4 (l / 16) + i][l % 16], i.e. cell l % 16
+// of planes 2 (l / 16) and 2 (l / 16) + 1.  The u and v kernel rows sit
+// back to back with three zeros between them (the zeros after a row are the
+// next row's leading ones), so every cell of a region the footprint meets
+// indexes a kernel value or a zero.  The region lists are packed back to
+// back; with these records four workgroups share a CU (LDS, and at most 128
+// registers a lane).
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -454,29 +513,33 @@ template <int ALPHA> struct GridStageMx {
     static constexpr int S = CH + 1;               // + the zero padding slot
     static constexpr int KP = ALPHA + 3;           // kernel row + the gap before the next one
     static constexpr int NKP = (S + 1) * KP + 16;  // rows 0..CH (row CH all zero) + zero tail
-    static constexpr int ND = 16;                  // dk values per visibility
-    static constexpr int LST = CH + 8;
+    static constexpr int NW = 8;                   // w weights per visibility (plane slots)
+    static constexpr int RPA = (ALPHA + 6) / 4 < 4 ? (ALPHA + 6) / 4 : 4;   // regions a footprint meets per axis
+    static constexpr int PAD = 4;                  // list entries read ahead
+    static constexpr int LSTT = (CH * RPA * RPA + 16 * (3 + PAD) + 15) & ~15;   // packed list capacity
     static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
     static constexpr size_t off_kv = al((size_t)NKP * sizeof(float));
-    static constexpr size_t off_dk = al(off_kv + (size_t)NKP * sizeof(float));
-    static constexpr size_t off_bs = al(off_dk + (size_t)S * ND * sizeof(float));
+    static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(float));
+    static constexpr size_t off_d = al(off_kw + (size_t)S * NW * sizeof(float));
+    static constexpr size_t off_bs = al(off_d + (size_t)S * sizeof(float2));
     static constexpr size_t off_list = al(off_bs + (size_t)S * sizeof(int2));
-    static constexpr size_t off_cnt = al(off_list + (size_t)16 * LST * sizeof(uint16_t));
+    static constexpr size_t off_cnt = al(off_list + (size_t)LSTT * sizeof(uint16_t));
     static constexpr size_t off_coef = al(off_cnt + (size_t)16 * 4 * sizeof(int));
     static constexpr size_t bytes = off_coef + kCoefBytes<float, ALPHA>;
 };
 
 template <int ALPHA, int PS>
-__global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra,
-                                                 int n_extra, int cap, float2 *__restrict__ G,
-                                                 float2 *__restrict__ part) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
+               float2 *__restrict__ G, float2 *__restrict__ part) {
     using ST = GridStageMx<ALPHA>;
-    constexpr int CH = ST::CH, KP = ST::KP, ND = ST::ND;
-    static_assert(2 * PS <= ND, "two dk values per plane slot");
+    constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW;
+    static_assert(PS <= NW, "one w weight per plane slot");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *s_ku = reinterpret_cast<float *>(smem_raw);                 // row v at 3 + v KP
     float *s_kv = reinterpret_cast<float *>(smem_raw + ST::off_kv);
-    float *s_dk = reinterpret_cast<float *>(smem_raw + ST::off_dk);    // [S][ND]
+    float *s_kw = reinterpret_cast<float *>(smem_raw + ST::off_kw);    // [S][NW] w weights on the plane slots
+    float *s_d = reinterpret_cast<float *>(smem_raw + ST::off_d);      // [S][2] weighted value
     int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);      // [S] row bases into s_ku / s_kv
     uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);
     int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);
@@ -517,12 +580,14 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
     In in{};
     if (first + tid < last) in = load_in(first + tid);
     // zero kernel rows and gaps (rows only ever overwrite their own ALPHA
-    // values), the zero slot's dk and row bases, the coefficient table
+    // values), the zero slot's value, w weights and row bases, the
+    // coefficient table
     for (int e = tid; e < ST::NKP; e += CH) {
         s_ku[e] = 0.f;
         s_kv[e] = 0.f;
     }
-    if (tid < ND) s_dk[CH * ND + tid] = 0.f;
+    if (tid < NW) s_kw[CH * NW + tid] = 0.f;
+    if (tid < 2) s_d[CH * 2 + tid] = 0.f;
     if (tid == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
     for (int e = tid; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
     f32x4 acc[4];
@@ -557,14 +622,17 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
 #pragma unroll
                 for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? 1.f : 0.f;
             }
-            float dk[ND];
+            float4 *pw = reinterpret_cast<float4 *>(s_kw + tid * NW);
 #pragma unroll
-            for (int n = 0; n < ND; ++n) dk[n] = n < 2 * PS ? ((n & 1) ? in.d.y : in.d.x) * ws[n >> 1] : 0.f;
-            float4 *pd = reinterpret_cast<float4 *>(s_dk + tid * ND);
-#pragma unroll
-            for (int n = 0; n < ND / 4; ++n) pd[n] = make_float4(dk[4 * n], dk[4 * n + 1], dk[4 * n + 2], dk[4 * n + 3]);
+            for (int n = 0; n < NW / 4; ++n) {
+                const int r0 = 4 * n;
+                pw[n] = make_float4(r0 < PS ? ws[r0 < PS ? r0 : 0] : 0.f, r0 + 1 < PS ? ws[r0 + 1 < PS ? r0 + 1 : 0] : 0.f,
+                                    r0 + 2 < PS ? ws[r0 + 2 < PS ? r0 + 2 : 0] : 0.f,
+                                    r0 + 3 < PS ? ws[r0 + 3 < PS ? r0 + 3 : 0] : 0.f);
+            }
+            reinterpret_cast<float2 *>(s_d)[tid] = in.d;
         }
-        build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
+        const int lbase = build_region_lists_packed<CH, ST::PAD>(bm, cm, tid, lane, wave, s_cnt, s_list);
         if (base + CH + tid < last) in = load_in(base + CH + tid);
         // ---- phase 2: one matrix product step per four visibilities ------
         // Two regions at a time (two independent accumulator chains and
@@ -579,15 +647,16 @@ __global__ __launch_bounds__(256) void k_grid_mx(VisArgs<float> a, int J, const 
             const int n4a = __builtin_amdgcn_readfirstlane((ca.x + ca.y + ca.z + ca.w + 3) & ~3);
             const int n4b = __builtin_amdgcn_readfirstlane((cb.x + cb.y + cb.z + cb.w + 3) & ~3);
             const int n4 = max(n4a, n4b);
-            const uint16_t *lsta = s_list + rga * ST::LST + kv_of;
-            const uint16_t *lstb = s_list + rgb * ST::LST + kv_of;
+            const uint16_t *lsta = s_list + __builtin_amdgcn_readlane(lbase, rga) + kv_of;
+            const uint16_t *lstb = s_list + __builtin_amdgcn_readlane(lbase, rgb) + kv_of;
             const int cola = 4 * qa + cc, colb = 4 * qb + cc;
             unsigned va = lsta[0], vb = lstb[0];
             int2 bsa = s_bs[va], bsb = s_bs[vb];
             for (int j = 0; j < n4; j += 4) {
                 const float kua = s_ku[bsa.x + row], kva = s_kv[bsa.y + cola];
                 const float kub = s_ku[bsb.x + row], kvb = s_kv[bsb.y + colb];
-                const float ava = s_dk[va * ND + m], avb = s_dk[vb * ND + m];
+                const float ava = s_d[2 * va + (m & 1)] * s_kw[va * NW + (m >> 1)];
+                const float avb = s_d[2 * vb + (m & 1)] * s_kw[vb * NW + (m >> 1)];
                 unsigned vna = lsta[min(j + 4, n4a)], vnb = lstb[min(j + 4, n4b)];
                 int2 bsna = s_bs[vna], bsnb = s_bs[vnb];
                 acc[qa] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, kua * kva, acc[qa], 0, 0, 0);
