@@ -138,6 +138,25 @@ def test_batch_boundaries(dev, ppb):
     assert rel(res["img"], ref["img"]) < 1e-13
 
 
+@pytest.mark.parametrize("ppb", [1, 3, 4, 5])
+def test_batch_boundaries_f32(dev, ppb):
+    """FP32 (matrix-core gridder): up to 4 planes per batch take the 4-slot
+    kernel, more the 8-slot one; the result matches the default batching
+    up to FP32 rounding and the same-plan oracle O2 within the kernel error."""
+    case = _case_small()
+    ref = run_product(case, 1e-5, "f32", torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=8, sigma=1.5)
+    res = run_product(case, 1e-5, "f32", torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=8, sigma=1.5,
+                      planes_per_batch=ppb)
+    assert res["info"]["planes_per_batch"] == ppb
+    assert rel(res["vis"], ref["vis"]) < 2e-6
+    assert rel(res["img"], ref["img"]) < 2e-6
+    pl = oracle_plan_from(res["info"], case)
+    i2 = o2.grid(case["uvw"], case["freq"], case["vis"], pl)
+    assert rel(res["img"], i2) < max(pl["eps_k"], 3e-6)
+    res["plan"].close()
+    ref["plan"].close()
+
+
 # ---------------------------------------------------------------------------
 # against the direct DFT (O1): rel L2 <= epsilon
 # ---------------------------------------------------------------------------
