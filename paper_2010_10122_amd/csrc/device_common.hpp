@@ -125,6 +125,27 @@ __device__ __forceinline__ void kernel_values_z3(R zu, R zv, R zw, const R *__re
     }
 }
 
+// sin and cos of 2 pi ph for ph in [-1/2, 1/2] (a phase in turns, already
+// reduced by its nearest integer in FP64), result in FP32.  The quarter
+// turn k = rint(4 ph) is split off in FP64, so the FP32 remainder
+// t = 2 pi (ph - k / 4) lies in [-pi/4, pi/4]; there the Taylor series of
+// sin (to t^9) and cos (to t^10) are truncated below 2e-9, under half an
+// FP32 ulp of the result; the quadrant then swaps and negates.
+__device__ __forceinline__ void sincos_turns_f32(double ph, float &sn, float &cs) {
+    const double k = rint(4.0 * ph);
+    const float t = (float)(kTwoPi * (ph - 0.25 * k));
+    const float t2 = t * t;
+    const float s = t * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f +
+                                                                                 t2 * (1.0f / 362880.0f)))));
+    const float c = 1.0f + t2 * (-0.5f + t2 * (1.0f / 24.0f + t2 * (-1.0f / 720.0f + t2 * (1.0f / 40320.0f +
+                                                                                       t2 * (-1.0f / 3628800.0f)))));
+    const int q = (int)k & 3;
+    const float s1 = (q & 1) ? c : s;
+    const float c1 = (q & 1) ? -s : c;
+    sn = (q & 2) ? -s1 : s1;
+    cs = (q & 2) ? -c1 : c1;
+}
+
 // blockIdx -> work-item remap that keeps neighbouring tiles on one XCD:
 // workgroups are dealt round-robin over the 8 XCDs, so give XCD x the
 // contiguous range [x * per, (x + 1) * per).  Returns -1 for padding blocks.

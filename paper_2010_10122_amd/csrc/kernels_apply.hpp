@@ -958,7 +958,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
                 double ph = cj * nm1[(int64_t)pp * pg.npix_y + q0 + col];
                 ph -= rint(ph);
                 R sn, cs;
-                if constexpr (sizeof(R) == 4) sincospif((float)(2.0 * ph), &sn, &cs);
+                if constexpr (sizeof(R) == 4) sincos_turns_f32(ph, sn, cs);
                 else sincospi(2.0 * ph, &sn, &cs);
                 val = hv.x * cs + hv.y * sn;      // Re(h * exp(-2 pi i ph))
             } else {
@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
                     double ph = cj * nrow[q];
                     ph -= rint(ph);
                     R sn, cs;
-                    if constexpr (sizeof(R) == 4) sincospif((float)(2.0 * ph), &sn, &cs);
+                    if constexpr (sizeof(R) == 4) sincos_turns_f32(ph, sn, cs);
                     else sincospi(2.0 * ph, &sn, &cs);
                     v = cmake<C>(x * cs, x * sn);
                 } else {
