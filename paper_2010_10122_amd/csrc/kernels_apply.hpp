@@ -761,61 +761,55 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
         j_first = max(j_lo, iw0);
         j_hi = min(j_hi, iw1 + ALPHA);
     }
-    // the first visibility of this thread: its inputs are read before the
-    // staging barrier, so that their latency overlaps the staging loads
-    int2 an_pf = make_int2(0, 0);
-    R zu_pf = 0, zv_pf = 0, zw_pf = 0;
-    if (s0 + tid < s1) {
-        const uint32_t s = s0 + tid;
-        an_pf = a.anc[s];
-        zu_pf = a.z[3 * (size_t)s];
-        zv_pf = a.z[3 * (size_t)s + 1];
-        zw_pf = a.z[3 * (size_t)s + 2];
-    }
-    // planes are staged PD at a time (tile + halo of PD planes in LDS)
-    for (int g0 = j_first; g0 < j_hi; g0 += PD) {
-        const int g1 = min(g0 + PD, j_hi);
-        const int np = g1 - g0;
-        for (int e = tid; e < np * W * W; e += blockDim.x) {
-            const int p = e / (W * W), cell = e - p * (W * W);
-            const int ra = cell / W, rb = cell - ra * W;
-            int ga = A * kTileCells + ra;
-            int gb = B * kTileCells + rb;
-            if (ga >= g.nu) ga -= g.nu;
-            if (gb >= g.nv) gb -= g.nv;
-            st[e] = G[((int64_t)(g0 - j_lo + p) * g.nu + ga) * g.nv + gb];
+    // One visibility per thread and chunk: its inputs are read before the
+    // chunk's first barrier, its kernel values once (while the first group
+    // of planes is staged), and its sum is kept in registers over the
+    // staged groups and added to the accumulator once.
+    for (uint32_t c0 = s0; c0 < s1; c0 += blockDim.x) {
+        const uint32_t s = c0 + tid;
+        bool act = s < s1;
+        int2 an = make_int2(0, 0);
+        R zu = 0, zv = 0, zw = 0;
+        C old = cmake<C>((R)0, (R)0);
+        if (act) {
+            an = a.anc[s];
+            zu = a.z[3 * (size_t)s];
+            zv = a.z[3 * (size_t)s + 1];
+            zw = a.z[3 * (size_t)s + 2];
+            old = visacc[s];
         }
-        __syncthreads();
-        for (uint32_t s = s0 + tid; s < s1; s += blockDim.x) {
-            int2 an;
-            R zu, zv, zw;
-            if (s == s0 + tid) {
-                an = an_pf;
-                zu = zu_pf;
-                zv = zv_pf;
-                zw = zw_pf;
-            } else {
-                an = a.anc[s];
-                zu = a.z[3 * (size_t)s];
-                zv = a.z[3 * (size_t)s + 1];
-                zw = a.z[3 * (size_t)s + 2];
+        const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
+        const int la0 = iu - A * kTileCells;   // in [0, 16) by the index
+        const int lb0 = iv - B * kTileCells;
+        act = act && la0 >= 0 && la0 < kTileCells && lb0 >= 0 && lb0 < kTileCells;
+        R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+        R sre = 0, sim = 0;
+        __syncthreads();                       // coefficients staged; previous chunk's readers done
+        // planes are staged PD at a time (tile + halo of PD planes in LDS)
+        for (int g0 = j_first; g0 < j_hi; g0 += PD) {
+            const int g1 = min(g0 + PD, j_hi);
+            const int np = g1 - g0;
+            if (g0 != j_first) __syncthreads();   // the previous group's readers are done
+            for (int e = tid; e < np * W * W; e += blockDim.x) {
+                const int p = e / (W * W), cell = e - p * (W * W);
+                const int ra = cell / W, rb = cell - ra * W;
+                int ga = A * kTileCells + ra;
+                int gb = B * kTileCells + rb;
+                if (ga >= g.nu) ga -= g.nu;
+                if (gb >= g.nv) gb -= g.nv;
+                st[e] = G[((int64_t)(g0 - j_lo + p) * g.nu + ga) * g.nv + gb];
             }
-            const int iu = an.x & 0xffff, iv = (an.x >> 16) & 0xffff, iw = an.y & 0x7fffffff;
-            const int la0 = iu - A * kTileCells;   // in [0, 16) by the index
-            const int lb0 = iv - B * kTileCells;
-            if (la0 < 0 || la0 >= kTileCells || lb0 < 0 || lb0 >= kTileCells) continue;
+            if (g0 == j_first && act) {
+                kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
+                if (!g.do_w) {
+#pragma unroll
+                    for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
+                }
+            }
+            __syncthreads();
             const int jw0 = g.do_w ? max(iw, g0) : g0;
             const int jw1 = g.do_w ? min(iw + ALPHA, g1) : g1;
-            if (jw0 >= jw1) continue;
-            // the running sum, read now and written back at the end
-            const C old = visacc[s];
-            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
-            if (!g.do_w) {
-#pragma unroll
-                for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
-            }
-            R sre = 0, sim = 0;
+            if (!act || jw0 >= jw1) continue;
             // the gather of one staged plane q with weight wq
             auto plane = [&](int q, R wq) {
                 const C *pl = st + q * (W * W) + la0 * W + lb0;
@@ -862,9 +856,8 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
                     plane(j - g0, kw[jw]);
                 }
             }
-            visacc[s] = cmake<C>(old.x + sre, old.y + sim);
         }
-        __syncthreads();
+        if (act) visacc[s] = cmake<C>(old.x + sre, old.y + sim);
     }
 }
 
