@@ -529,7 +529,7 @@ template <int ALPHA> struct GridStageMx {
 };
 
 template <int ALPHA, int PS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ALPHA <= 8 ? 4 : 1)))
 void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
                float2 *__restrict__ G, float2 *__restrict__ part) {
     using ST = GridStageMx<ALPHA>;

@@ -84,7 +84,8 @@ def test_binning_and_plan_bit_exact(dev, which):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("alpha,sigma,prec", [(16, 1.35, "f64"), (12, 1.5, "f64"), (8, 1.45, "f32"),
-                                              (7, 1.5, "f32"), (4, 2.0, "f64"), (8, 1.45, "f64")])
+                                              (7, 1.5, "f32"), (4, 2.0, "f64"), (8, 1.45, "f64"),
+                                              (12, 1.5, "f32")])
 def test_same_plan_as_o2(dev, alpha, sigma, prec):
     case = _case_small()
     print(f"[o2] alpha={alpha} sigma={sigma} {prec}", flush=True)
