@@ -40,6 +40,7 @@ extern "C" {
 #define WG_EHIP         -3   /* a HIP runtime call or kernel launch failed            */
 #define WG_EUNSUPPORTED -4   /* valid request outside what this library implements   */
 
+
 /* ---- precision --------------------------------------------------------- */
 #define WG_F32 0   /* complex64 visibilities, float32 image (epsilon >= 1e-5)      */
 #define WG_F64 1   /* complex128 visibilities, float64 image (epsilon > 2e-13)     */
@@ -68,10 +69,14 @@ typedef struct {
     double         epsilon;      /* requested accuracy (relative L2)                    */
     int            precision;    /* WG_F32 or WG_F64                                    */
     int            do_wgridding; /* 0: w treated as zero (narrow field), else w-gridding */
-    int            alpha;        /* 0 = automatic; else force kernel support (4,7,8,12,16) */
-    double         sigma;        /* 0 = automatic; else force oversampling (table row)  */
+    int            alpha;        /* 0 = automatic; else force kernel support (4..16)    */
+    double         sigma;        /* 0 = automatic; else force oversampling (a row of the
+                                    planner's table, see wg_kernel_table)               */
     int            planes_per_batch; /* 0 = automatic; w-planes processed per batch,
                                         capped at alpha and at 8 (FP32) / 4 (FP64)      */
+    int            fft_path;     /* 0 = automatic (full-length column passes); 1 = the
+                                    same; 2 = u transform split in two (four-step),
+                                    where the sizes allow it, else as 1                */
     void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
     wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
     wg_free_fn     free;
@@ -84,7 +89,8 @@ typedef struct {
  * dw = 1/(2 sigma max|n-1|), the first plane w_o and the plane count N_w
  * (Sect. 2, eq. wcirc), builds the piecewise-polynomial kernel (Sect. 4.2),
  * the correction factors and the visibility index (Sect. 4.3) on the device.
- * Synchronises the stream once (to read the w range and the active count).
+ * Synchronises the stream a few times (w range, index sizes) and returns
+ * when the plan is complete.
  * The uvw/freq/mask arrays are read during creation and again by every
  * apply call: they must stay alive and unchanged while the plan is used.
  * Errors: WG_EINVAL for NULL desc/out/uvw/freq, odd or < 32 npix, pixsize
@@ -94,9 +100,25 @@ typedef struct {
  *   epsilon or the grid exceeds the FFT size limit; WG_ENOMEM, WG_EHIP. */
 int wg_plan_create(const wg_plan_desc *desc, wg_plan **out);
 
-/* Destroy a plan and release its device memory (after synchronising the
- * plan's stream).  NULL is accepted. */
+/* Destroy a plan and release its device memory.  No apply call using the
+ * plan may still be running on any stream.  Without allocator callbacks the
+ * memory goes back through hipFree (which waits for the device); with them,
+ * every block is handed to the free callback at once.  NULL is accepted. */
 int wg_plan_destroy(wg_plan *plan);
+
+/* Footprint of the plan wg_plan_create would build for desc, without
+ * building it (for admission by memory: Sect. 4.3 index, Sect. 2 geometry).
+ * Runs the w-range reduction on desc->stream and synchronises it once;
+ * every other step is host planning.  Outputs (each may be NULL):
+ *   plan_bytes       upper bound of wg_plan_bytes of the built plan
+ *   peak_bytes       upper bound of the device bytes held while it is built
+ *                    (plan_bytes plus the sort scratch)
+ *   workspace_bytes  upper bound of wg_workspace_bytes (loose: the gridder's
+ *                    partial-tile scratch depends on the binning; use the
+ *                    built plan's exact figure to admit apply calls)
+ * Errors as wg_plan_create (WG_EINVAL, WG_EUNSUPPORTED, WG_ENOMEM, WG_EHIP). */
+int wg_plan_estimate(const wg_plan_desc *desc, size_t *plan_bytes, size_t *peak_bytes,
+                     size_t *workspace_bytes);
 
 /* Degridding (forward, eq. R3 with R1, R2): vis = wgt * R(dirty).
  *   dirty     device [npix_x][npix_y] float32 (WG_F32) or float64 (WG_F64)
@@ -143,6 +165,14 @@ typedef struct {
     size_t  workspace_bytes;  /* per apply call                                       */
     int64_t extra_items_grid; /* gridder work items beyond one per tile, all batches  */
     int64_t extra_items_degrid;/* likewise for the degridder                          */
+    double  rounding_error;   /* estimated relative rounding error of one apply in the
+                                 plan's precision: 1.2 ulp x amplification          */
+    double  amplification;    /* rms over the image of Psi(0)/Psi: the factor by which
+                                 the correction 1/(n Psi) (Sect. 2) magnifies errors
+                                 made on the grid                                    */
+    double  poly_error;       /* largest |polynomial - phi| over the alpha cells of the
+                                 piecewise kernel (Sect. 4.2), evaluated in FP64      */
+    int     fft_split;        /* rows per u-split stage S (0: full-length column passes) */
 } wg_plan_info_t;
 
 int    wg_plan_info(const wg_plan *plan, wg_plan_info_t *info);
@@ -193,8 +223,9 @@ const char *wg_kernel_kind_name(int kind);
  * for the FFT).  Returns N, or WG_EINVAL. */
 int wg_grid_size(double sigma, int npix);
 
-/* Modified-ES parameters of a printed Appendix-A row.  Returns WG_EINVAL when
- * (alpha, sigma) is not a printed row. */
+/* Modified-ES parameters of a row of the planner's table (Appendix A where
+ * printed, else the searched row).  Returns WG_EINVAL when (alpha, sigma) is
+ * not in the table. */
 int wg_kernel_params(int alpha, double sigma, double *eps_k, double *beta, double *mu);
 
 /* Kernel choice for a problem (Sect. 4.1): for each support the smallest
@@ -210,6 +241,27 @@ int wg_select_kernel(double epsilon, int precision, int do_wgridding, int npix_x
  * sum_d coeffs[i*(degree+1) + d] * z^d.  Fills at most cap doubles;
  * *degree receives the degree.  Interpolation at Chebyshev roots. */
 int wg_kernel_poly(int alpha, double sigma, int precision, double *coeffs, int cap, int *degree);
+
+/* Two-parameter kernel search of Sect. 3.2: the (beta, mu) of the modified
+ * ES kernel (eq. semicircle2) that minimise the supremum over the retained
+ * band 0 <= x <= 1/(2 sigma) of the map error function l(x) (eq. maperror),
+ * for support alpha (2..16 cells) and oversampling sigma (1 < sigma <= 4).
+ * On input, *beta and *mu > 0 add a starting point (e.g. the optimum of a
+ * neighbouring sigma) to the search's own; 0 adds none.  eps (may be NULL)
+ * receives the supremum at the result.  Host only; takes seconds.
+ * Errors: WG_EINVAL. */
+int wg_kernel_search(int alpha, double sigma, double *beta, double *mu, double *eps);
+
+/* Supremum of the map error function (eq. maperror) over the retained band
+ * for given kernel parameters (host only).  Errors: WG_EINVAL. */
+int wg_kernel_map_error(int alpha, double sigma, double beta, double mu, double *eps);
+
+/* Row `index` (0-based) of the planner's kernel table, sorted by alpha then
+ * sigma: the printed Appendix-A rows and, for the (alpha, sigma) pairs the
+ * paper does not print, rows of wg_kernel_search generated at build time.
+ * printed receives 1 for an Appendix-A row.  Any output may be NULL.
+ * Returns WG_EINVAL past the end. */
+int wg_kernel_table(int index, int *alpha, double *sigma, double *eps, double *beta, double *mu, int *printed);
 
 /* Fourier transform of the kernel, psi(k) = int phi(t) cos(2 pi k t) dt, at
  * n points (host arrays). */

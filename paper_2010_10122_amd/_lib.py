@@ -29,6 +29,7 @@ class PlanDesc(ctypes.Structure):
         ("alpha", ctypes.c_int),
         ("sigma", ctypes.c_double),
         ("planes_per_batch", ctypes.c_int),
+        ("fft_path", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("alloc", _alloc_fn),
         ("free", _free_fn),
@@ -68,13 +69,18 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("extra_items_grid", ctypes.c_int64),
         ("extra_items_degrid", ctypes.c_int64),
+        ("rounding_error", ctypes.c_double),
+        ("amplification", ctypes.c_double),
+        ("poly_error", ctypes.c_double),
+        ("fft_split", ctypes.c_int),
     ]
 
 
 EXPORTS = [
-    "wg_plan_create", "wg_plan_destroy", "wg_degrid", "wg_grid", "wg_plan_info",
+    "wg_plan_create", "wg_plan_destroy", "wg_plan_estimate", "wg_degrid", "wg_grid", "wg_plan_info",
     "wg_workspace_bytes", "wg_plan_bytes", "wg_plan_index", "wg_strerror", "wg_grid_size",
-    "wg_kernel_params", "wg_select_kernel", "wg_kernel_poly", "wg_kernel_psi",
+    "wg_kernel_params", "wg_select_kernel", "wg_kernel_poly", "wg_kernel_psi", "wg_kernel_search",
+    "wg_kernel_map_error", "wg_kernel_table",
     "wg_profiler_create", "wg_profiler_destroy", "wg_profiler_attach", "wg_profiler_read",
     "wg_profiler_reset", "wg_kernel_kind_name",
 ]
@@ -106,6 +112,9 @@ def load():
     lib.wg_plan_create.restype = ctypes.c_int
     lib.wg_plan_destroy.argtypes = [vp]
     lib.wg_plan_destroy.restype = ctypes.c_int
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    lib.wg_plan_estimate.argtypes = [ctypes.POINTER(PlanDesc), sz, sz, sz]
+    lib.wg_plan_estimate.restype = ctypes.c_int
     for fn in (lib.wg_degrid, lib.wg_grid):
         fn.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         fn.restype = ctypes.c_int
@@ -131,6 +140,12 @@ def load():
     lib.wg_kernel_poly.restype = ctypes.c_int
     lib.wg_kernel_psi.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, dp]
     lib.wg_kernel_psi.restype = ctypes.c_int
+    lib.wg_kernel_search.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
+    lib.wg_kernel_search.restype = ctypes.c_int
+    lib.wg_kernel_map_error.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    lib.wg_kernel_map_error.restype = ctypes.c_int
+    lib.wg_kernel_table.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp, ip]
+    lib.wg_kernel_table.restype = ctypes.c_int
     lib.wg_profiler_create.argtypes = [ctypes.POINTER(vp)]
     lib.wg_profiler_create.restype = ctypes.c_int
     lib.wg_profiler_destroy.argtypes = [vp]

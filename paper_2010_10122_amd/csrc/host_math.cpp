@@ -10,13 +10,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <limits>
 #include <vector>
 
 namespace wg {
 
 // Appendix A, "Kernel parameters": {alpha, sigma, eps, beta, mu}.
-static const KernelRow kTable[] = {
+static const KernelRow kPrinted[] = {
     { 4, 1.15, 0.025654879, 1.3873426689, 0.5436851297},
     { 4, 1.2, 0.013809249, 1.3008419165, 0.5902137484},
     { 4, 1.25, 0.0085840685, 1.3274088935, 0.5953499486},
@@ -105,16 +106,44 @@ static const KernelRow kTable[] = {
     {16, 2.0, 5.0563492e-15, 2.2621631913, 0.5056924675},
 };
 
-const int kSupports[kNumSupports] = {4, 7, 8, 12, 16};
+// Rows of the library's own search of the map error (Sect. 3.2) for every
+// support 4..16 and sigma 1.15..2.00, generated by gen_kernel_table.py.
+static const KernelRow kSearched[] = {
+#include "kernel_table_search.inc"
+    {0, 0.0, 0.0, 0.0, 0.0}   // end marker
+};
+
+const int kSupports[kNumSupports] = {4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+
+bool is_printed(int alpha, double sigma) {
+    for (const KernelRow &r : kPrinted)
+        if (r.alpha == alpha && std::fabs(r.sigma - sigma) < 1e-9) return true;
+    return false;
+}
+
+// The planner's table: the printed rows, and the searched rows of the
+// (alpha, sigma) pairs the paper does not print; sorted by alpha, then sigma.
+const std::vector<KernelRow> &planner_table() {
+    static const std::vector<KernelRow> table = [] {
+        std::vector<KernelRow> t(std::begin(kPrinted), std::end(kPrinted));
+        for (const KernelRow &r : kSearched)
+            if (r.alpha > 0 && !is_printed(r.alpha, r.sigma)) t.push_back(r);
+        std::sort(t.begin(), t.end(), [](const KernelRow &a, const KernelRow &b) {
+            return a.alpha != b.alpha ? a.alpha < b.alpha : a.sigma < b.sigma;
+        });
+        return t;
+    }();
+    return table;
+}
 
 const KernelRow *find_row(int alpha, double sigma) {
-    for (const KernelRow &r : kTable)
+    for (const KernelRow &r : planner_table())
         if (r.alpha == alpha && std::fabs(r.sigma - sigma) < 1e-9) return &r;
     return nullptr;
 }
 
 const KernelRow *smallest_feasible(int alpha, double eps, double factor) {
-    for (const KernelRow &r : kTable)
+    for (const KernelRow &r : planner_table())
         if (r.alpha == alpha && factor * r.eps <= eps) return &r;   // rows ascend in sigma
     return nullptr;
 }
@@ -333,6 +362,182 @@ double rounding_error(int alpha, double sigma, int precision, int do_w, int npix
     return 1.2 * ulp * rounding_amplification(alpha, sigma, do_w, npix_x, npix_y, px, py);
 }
 
+// ---- kernel-parameter search (Sect. 3.2) --------------------------------
+// Map error function of eq. (maperror): for a frequency x in grid units
+// (|x| <= 1/(2 sigma) is the retained band),
+//   l(x)^2 = int_0^1 | 1 - sum_{a in U(nu)} phi(a - nu) e^{2 pi i (a - nu) x} / psi(x) |^2 dnu,
+// where U(nu) are the alpha cells the kernel of a point at fractional
+// position nu touches (a = ceil(nu - alpha/2) + i).  The set U changes at
+// nu = frac(alpha/2), so the nu integral is split there; each piece uses
+// tanh-sinh nodes, which follow the (alpha/2 - |t|)^mu edge behaviour of
+// the kernel.  psi by the planner's own tanh-sinh quadrature (psi_nodes).
+namespace {
+struct NuRule {
+    std::vector<double> nu, w;
+};
+NuRule nu_rule(int alpha) {
+    NuRule r;
+    const double brk = std::fmod(0.5 * alpha, 1.0);
+    std::vector<std::pair<double, double>> segs;
+    if (brk == 0.0) segs.push_back({0.0, 1.0});
+    else {
+        segs.push_back({0.0, brk});
+        segs.push_back({brk, 1.0});
+    }
+    const double h = 1.0 / 12.0;
+    for (auto sg : segs) {
+        const double a = sg.first, b = sg.second, c = 0.5 * (a + b), hw = 0.5 * (b - a);
+        for (int k = -48; k <= 48; ++k) {
+            const double x = k * h;
+            const double u = 0.5 * M_PI * std::sinh(x);
+            const double t = std::tanh(u);
+            const double wt = h * 0.5 * M_PI * std::cosh(x) / (std::cosh(u) * std::cosh(u));
+            if (wt < 1e-18 || std::fabs(t) >= 1.0) continue;
+            r.nu.push_back(c + hw * t);
+            r.w.push_back(hw * wt);
+        }
+    }
+    return r;
+}
+}  // namespace
+
+double map_error(double x, int alpha, double beta, double mu, const std::vector<double> &qt,
+                 const std::vector<double> &qw) {
+    static thread_local int cached_alpha = -1;
+    static thread_local NuRule rule;
+    if (cached_alpha != alpha) {
+        rule = nu_rule(alpha);
+        cached_alpha = alpha;
+    }
+    const double ps = psi_eval(x, qt, qw);
+    double acc = 0.0;
+    for (size_t k = 0; k < rule.nu.size(); ++k) {
+        const double nu = rule.nu[k];
+        const double a0 = std::ceil(nu - 0.5 * alpha);
+        double sr = 0.0, si = 0.0;
+        for (int i = 0; i < alpha; ++i) {
+            const double off = a0 + i - nu;                      // a - nu in [-alpha/2, alpha/2)
+            const double ph = es_kernel(off, alpha, beta, mu);
+            const double ang = 2.0 * M_PI * off * x;
+            sr += ph * std::cos(ang);
+            si += ph * std::sin(ang);
+        }
+        const double dr = 1.0 - sr / ps, di = -si / ps;
+        acc += rule.w[k] * (dr * dr + di * di);
+    }
+    return std::sqrt(acc);
+}
+
+double map_error_sup(int alpha, double sigma, double beta, double mu) {
+    std::vector<double> qt, qw;
+    psi_nodes(alpha, beta, mu, qt, qw);
+    const double xmax = 0.5 / sigma;
+    const int nx = 160;
+    std::vector<double> xs(nx + 1), ls(nx + 1);
+    for (int i = 0; i <= nx; ++i) {
+        xs[i] = xmax * i / nx;
+        ls[i] = map_error(xs[i], alpha, beta, mu, qt, qw);
+    }
+    // The minimax optimum equioscillates: refine every local maximum of the
+    // samples (golden section on its bracket), not only the largest one.
+    double top = 0.0;
+    for (int i = 0; i <= nx; ++i) {
+        top = std::max(top, ls[i]);
+        const bool peak = (i == 0 || ls[i] >= ls[i - 1]) && (i == nx || ls[i] >= ls[i + 1]);
+        if (!peak) continue;
+        double lo = xs[std::max(0, i - 1)], hi = xs[std::min(nx, i + 1)];
+        const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+        double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+        double f1 = map_error(x1, alpha, beta, mu, qt, qw), f2 = map_error(x2, alpha, beta, mu, qt, qw);
+        for (int it = 0; it < 24; ++it) {
+            if (f1 > f2) {
+                hi = x2; x2 = x1; f2 = f1; x1 = hi - g * (hi - lo); f1 = map_error(x1, alpha, beta, mu, qt, qw);
+            } else {
+                lo = x1; x1 = x2; f1 = f2; x2 = lo + g * (hi - lo); f2 = map_error(x2, alpha, beta, mu, qt, qw);
+            }
+        }
+        top = std::max(top, std::max(f1, f2));
+    }
+    return top;
+}
+
+// Two-parameter search of Sect. 3.2: (beta, mu) minimising the supremum of
+// l(x) over the retained band, for a given support and oversampling.  A
+// coarse grid over the range the printed tables occupy (plus an optional
+// caller start, e.g. the optimum of the neighbouring sigma), then
+// Nelder-Mead on log sup l, restarted from its own result with a fresh
+// simplex until a restart no longer improves (the objective is a maximum of
+// equioscillating peaks, not smooth, and a single simplex can stall).
+namespace {
+double nelder_mead(const std::function<double(double, double)> &f, double &b, double &m, double fb, double db,
+                   double dm) {
+    double P[3][2] = {{b, m}, {b + db, m}, {b, m + dm}};
+    double F[3] = {fb, f(P[1][0], P[1][1]), f(P[2][0], P[2][1])};
+    for (int it = 0; it < 200; ++it) {
+        int o[3] = {0, 1, 2};
+        std::sort(o, o + 3, [&](int x, int y) { return F[x] < F[y]; });
+        const int lo = o[0], mid = o[1], hi = o[2];
+        if (std::fabs(F[hi] - F[lo]) < 1e-9 && std::fabs(P[hi][0] - P[lo][0]) + std::fabs(P[hi][1] - P[lo][1]) < 1e-7)
+            break;
+        const double c0 = 0.5 * (P[lo][0] + P[mid][0]), c1 = 0.5 * (P[lo][1] + P[mid][1]);
+        const double r0 = 2.0 * c0 - P[hi][0], r1 = 2.0 * c1 - P[hi][1];
+        const double fr = f(r0, r1);
+        if (fr < F[lo]) {
+            const double e0 = 3.0 * c0 - 2.0 * P[hi][0], e1 = 3.0 * c1 - 2.0 * P[hi][1];
+            const double fe = f(e0, e1);
+            if (fe < fr) { P[hi][0] = e0; P[hi][1] = e1; F[hi] = fe; }
+            else { P[hi][0] = r0; P[hi][1] = r1; F[hi] = fr; }
+        } else if (fr < F[mid]) {
+            P[hi][0] = r0; P[hi][1] = r1; F[hi] = fr;
+        } else {
+            const double k0 = 0.5 * (c0 + P[hi][0]), k1 = 0.5 * (c1 + P[hi][1]);
+            const double fk = f(k0, k1);
+            if (fk < F[hi]) { P[hi][0] = k0; P[hi][1] = k1; F[hi] = fk; }
+            else {
+                for (int j : {mid, hi}) {
+                    P[j][0] = 0.5 * (P[j][0] + P[lo][0]);
+                    P[j][1] = 0.5 * (P[j][1] + P[lo][1]);
+                    F[j] = f(P[j][0], P[j][1]);
+                }
+            }
+        }
+    }
+    int best = 0;
+    for (int j = 1; j < 3; ++j) if (F[j] < F[best]) best = j;
+    b = P[best][0];
+    m = P[best][1];
+    return F[best];
+}
+}  // namespace
+
+double kernel_search(int alpha, double sigma, double *beta, double *mu) {
+    auto f = [&](double b, double m) {
+        if (!(b > 0.3 && b < 4.0 && m > 0.2 && m < 1.0)) return 1e300;
+        return std::log(map_error_sup(alpha, sigma, b, m));
+    };
+    struct Start { double f, b, m; };
+    std::vector<Start> starts;
+    for (double b = 1.1; b <= 2.6 + 1e-9; b += 0.1)
+        for (double m = 0.47; m <= 0.62 + 1e-9; m += 0.025) starts.push_back({f(b, m), b, m});
+    std::sort(starts.begin(), starts.end(), [](const Start &x, const Start &y) { return x.f < y.f; });
+    starts.resize(std::min<size_t>(starts.size(), 2));
+    if (*beta > 0.0 && *mu > 0.0) starts.push_back({f(*beta, *mu), *beta, *mu});
+    double bf = 1e300, bb = 0.0, bm = 0.0;
+    for (const Start &st : starts) {
+        double b = st.b, m = st.m, fb = st.f;
+        for (int restart = 0; restart < 6; ++restart) {
+            const double fn = nelder_mead(f, b, m, fb, 0.03 / (1 + restart), 0.006 / (1 + restart));
+            const bool better = fn < fb - 1e-6;
+            fb = std::min(fb, fn);
+            if (!better) break;
+        }
+        if (fb < bf) { bf = fb; bb = b; bm = m; }
+    }
+    *beta = bb;
+    *mu = bm;
+    return std::exp(bf);
+}
+
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,
                   double py, int64_t n_vis, double wmin, double wmax, int *alpha,
                   double *sigma, double *seconds) {
@@ -346,7 +551,7 @@ int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, d
         // smallest printed sigma whose kernel error plus the estimated
         // rounding error of this precision stays within eps
         const KernelRow *r = nullptr;
-        const KernelRow *end = kTable + sizeof(kTable) / sizeof(kTable[0]);
+        const KernelRow *end = planner_table().data() + planner_table().size();
         for (const KernelRow *c = smallest_feasible(a, eps, factor); c && c < end && c->alpha == a; ++c) {
             if (factor * c->eps + rounding_error(a, c->sigma, precision, do_w, npix_x, npix_y, px, py) <= eps) {
                 r = c;

@@ -6,7 +6,7 @@
 namespace wg {
 
 constexpr int kTile = 16;          // uv tile edge of the visibility index (Sect. 4.3)
-constexpr int kNumSupports = 5;    // printed supports of Appendix A
+constexpr int kNumSupports = 13;   // supports 4..16 (printed rows of Appendix A, searched rows otherwise)
 // Largest grid edge per precision: one strided transform line of K >= 1
 // columns must fit the column-pass workgroup (FP32 12288, FP64 6144 values).
 constexpr int kMaxGridF32 = 12288;
@@ -19,6 +19,8 @@ struct KernelRow {
     double sigma, eps, beta, mu;
 };
 
+const std::vector<KernelRow> &planner_table();
+bool is_printed(int alpha, double sigma);
 const KernelRow *find_row(int alpha, double sigma);
 const KernelRow *smallest_feasible(int alpha, double eps, double factor);
 int good_size(long long nmin);
@@ -37,6 +39,10 @@ double rounding_amplification(int alpha, double sigma, int do_w, int npix_x, int
                               double py);
 double rounding_error(int alpha, double sigma, int precision, int do_w, int npix_x, int npix_y, double px,
                       double py);
+double map_error(double x, int alpha, double beta, double mu, const std::vector<double> &qt,
+                 const std::vector<double> &qw);
+double map_error_sup(int alpha, double sigma, double beta, double mu);
+double kernel_search(int alpha, double sigma, double *beta, double *mu);
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,
                   double py, int64_t n_vis, double wmin, double wmax, int *alpha, double *sigma,
                   double *seconds);

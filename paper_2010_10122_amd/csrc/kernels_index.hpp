@@ -42,6 +42,14 @@ __global__ void k_wrange(const double *__restrict__ uvw, const double *__restric
     }
 }
 
+__global__ void k_wrange_init(unsigned long long *out) {
+    if (threadIdx.x == 0) {
+        out[0] = ~0ull;
+        out[1] = 0ull;
+        out[2] = 0ull;
+    }
+}
+
 // ---- binning keys: ((t_u * NTv + t_v) * N_w + t_w), masked -> sentinel ----
 __global__ void k_keys(const double *__restrict__ uvw, const double *__restrict__ scale,
                        const uint8_t *__restrict__ mask, int64_t n_rows, Geom g,

@@ -15,7 +15,10 @@
 #include "../../include/wgrid.h"
 #include "host_math.hpp"
 #include "kernels_apply.hpp"
+#include "fft_split.hpp"
 #include "kernels_index.hpp"
+#include "plan_internal.hpp"
+#include "vis_launch.hpp"
 
 using namespace wg;
 
@@ -109,39 +112,6 @@ struct ProfScope {
     }
 };
 
-struct DevMem {
-    wg_alloc_fn alloc = nullptr;
-    wg_free_fn free = nullptr;
-    void *ctx = nullptr;
-    size_t total = 0;                          // bytes currently held
-    std::unordered_map<void *, size_t> sizes;
-    void *get(size_t bytes) {
-        if (bytes == 0) bytes = 16;
-        void *p = nullptr;
-        if (alloc) {
-            p = alloc(ctx, bytes);
-        } else if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-        }
-        if (p) {
-            total += bytes;
-            sizes[p] = bytes;
-        }
-        return p;
-    }
-    void put(void *p) {
-        if (!p) return;
-        auto it = sizes.find(p);
-        if (it != sizes.end()) {
-            total -= it->second;
-            sizes.erase(it);
-        }
-        if (free) free(ctx, p);
-        else (void)hipFree(p);
-    }
-};
-
 int64_t grid_blocks(int64_t n, int threads, int64_t cap = 65536) {
     int64_t b = (n + threads - 1) / threads;
     return std::max<int64_t>(1, std::min(b, cap));
@@ -200,64 +170,37 @@ void twiddles(int n, std::vector<double> &re, std::vector<double> &im) {
 
 }  // namespace
 
-struct wg_plan {
-    wg_plan_desc desc;
-    DevMem mem;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    // kernel
-    int alpha = 0, degree = 0, precision = 0, do_w = 0;
-    double sigma = 0, beta = 0, mu = 0, eps_k = 0;
-    // geometry
-    Geom g{};
-    int P = 1, NJ = 1;
-    int64_t n_total = 0, n_active = 0;
-    double wmin = 0, wmax = 0, predicted = 0;
-    FftDesc fft_u{}, fft_v{};
-    int k_cols = 1;     // columns per workgroup in the strided passes
-    int k_cols_d = 1;   // the same for the degridding column pass
-    // device arrays
-    double *scale = nullptr;           // [n_chan]
-    void *coef = nullptr;              // [degree+1][alpha] R
-    void *tw_u = nullptr, *tw_v = nullptr;   // complex R
-    double *nm1 = nullptr, *corr = nullptr;  // [npix_x][npix_y]
-    unsigned long long *keys = nullptr;
-    uint32_t *order = nullptr;
-    uint32_t *tab_lo = nullptr, *tab_hi = nullptr;
-    void *zc = nullptr;                // [n_active][3] R: kernel-local coordinates
-    int2 *anc = nullptr;               // [n_active] anchors and fold bit
-    uint32_t *inv = nullptr;           // [n_total] sorted position | fold << 31, ~0 if masked
-    // extra work items per batch (lists longer than the item cap); offsets into
-    // the device lists, [NJ + 1] each
-    std::vector<uint32_t> xg_off, xd_off, xr_off;
-    int4 *xg = nullptr, *xd = nullptr, *xr = nullptr;
-    int max_slots = 0;                 // partial tiles of the gridder in one batch
-    size_t index_bytes = 0;
-    size_t ws_bytes = 0;
-    // workspace layout (byte offsets)
-    size_t off_G = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
-};
 
 namespace {
 
 
 template <typename R> int build_plan_tables(wg_plan *p, const std::vector<double> &coefd,
                                             const std::vector<double> &twu_re, const std::vector<double> &twu_im,
-                                            const std::vector<double> &twv_re, const std::vector<double> &twv_im) {
+                                            const std::vector<double> &twv_re, const std::vector<double> &twv_im,
+                                            const std::vector<double> &tw1_re, const std::vector<double> &tw1_im) {
     using C = Cx<R>;
     std::vector<R> cr(coefd.size());
     for (size_t i = 0; i < coefd.size(); ++i) cr[i] = (R)coefd[i];
+    const hipStream_t st = p->stream;
     p->coef = p->mem.get(cr.size() * sizeof(R));
     if (!p->coef) return WG_ENOMEM;
-    HIP_TRY(hipMemcpy(p->coef, cr.data(), cr.size() * sizeof(R), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p->coef, cr.data(), cr.size() * sizeof(R), hipMemcpyHostToDevice, st));
     std::vector<C> tu(twu_re.size()), tv(twv_re.size());
     for (size_t i = 0; i < tu.size(); ++i) { tu[i].x = (R)twu_re[i]; tu[i].y = (R)twu_im[i]; }
     for (size_t i = 0; i < tv.size(); ++i) { tv[i].x = (R)twv_re[i]; tv[i].y = (R)twv_im[i]; }
     p->tw_u = p->mem.get(tu.size() * sizeof(C));
     p->tw_v = p->mem.get(tv.size() * sizeof(C));
     if (!p->tw_u || !p->tw_v) return WG_ENOMEM;
-    HIP_TRY(hipMemcpy(p->tw_u, tu.data(), tu.size() * sizeof(C), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->tw_v, tv.data(), tv.size() * sizeof(C), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p->tw_u, tu.data(), tu.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->tw_v, tv.data(), tv.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    std::vector<C> t1(tw1_re.size());
+    if (!t1.empty()) {
+        for (size_t i = 0; i < t1.size(); ++i) { t1[i].x = (R)tw1_re[i]; t1[i].y = (R)tw1_im[i]; }
+        p->tw_u1 = p->mem.get(t1.size() * sizeof(C));
+        if (!p->tw_u1) return WG_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(p->tw_u1, t1.data(), t1.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));   // the host vectors must outlive the copies
     return WG_OK;
 }
 
@@ -399,20 +342,98 @@ int validate(const wg_plan_desc *d) {
         if (!find_row(d->alpha, d->sigma)) return WG_EINVAL;
     }
     if (d->planes_per_batch < 0) return WG_EINVAL;
+    if (d->fft_path < 0 || d->fft_path > 2) return WG_EINVAL;
     double l = (double)(0 - d->npix_x / 2) * d->pixsize_x;
     double m = (double)(0 - d->npix_y / 2) * d->pixsize_y;
     if (!(l * l + m * m < 1.0)) return WG_EINVAL;
     return WG_OK;
 }
 
-int plan_build(wg_plan *p) {
-    const wg_plan_desc &d = p->desc;
-    hipStream_t st = p->stream;
-    HIP_TRY(hipGetDevice(&p->device));
-    p->precision = d.precision;
-    p->do_w = d.do_wgridding ? 1 : 0;
-    p->n_total = d.n_rows * d.n_chan;
-    // channel scale freq / c on the host (same IEEE division as everywhere)
+// Workspace layout of one apply call (byte offsets into the caller's
+// workspace) for a given number of partial-tile slots of the gridder.
+size_t plan_layout(wg_plan *p, int64_t slots) {
+    const Geom &g = p->g;
+    const size_t sc = p->precision == WG_F32 ? 8 : 16;
+    const size_t sr = sc / 2;
+    const int64_t npix = (int64_t)g.npix_x * g.npix_y;
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    p->off_G = off;
+    off = align(off + (size_t)p->P * g.nu * g.nv * sc);
+    p->off_T = off;
+    off = align(off + (size_t)p->P * std::max((size_t)g.nu * g.npix_y, (size_t)g.npix_x * g.nv) * sc);
+    p->off_acc = off;
+    off = align(off + (size_t)npix * sr);
+    p->off_itil = off;
+    off = align(off + (size_t)npix * sr);
+    p->off_vacc = off;
+    off = align(off + (size_t)std::max<int64_t>(p->n_active, 1) * sc);
+    p->off_part = off;
+    off = align(off + (size_t)slots * p->P * kTile * kTile * sc);
+    p->ws_bytes = off;
+    return off;
+}
+
+// Device bytes the plan holds once built (resident) and at most during
+// construction (peak), from the geometry alone.  Work-item lists, whose
+// length depends on the binning, are bounded by their largest possible size.
+void plan_footprint(const wg_plan *p, size_t &resident, size_t &peak) {
+    const Geom &g = p->g;
+    const size_t sc = p->precision == WG_F32 ? 8 : 16;
+    const size_t sr = sc / 2;
+    const uint64_t npix = (uint64_t)g.npix_x * g.npix_y;
+    const uint64_t ntot = (uint64_t)std::max<int64_t>(p->n_total, 1);
+    const uint64_t nact = (uint64_t)std::max<int64_t>(p->n_active, 1);
+    const uint64_t ntiles = (uint64_t)g.ntu * g.ntv;
+    const uint64_t tab_n = ntiles * (uint64_t)(p->NJ + 1);
+    const uint64_t span = (uint64_t)((p->alpha - 1 + p->P - 1) / p->P + 1);   // batches a visibility meets
+    const uint64_t items = 3 * (4 * nact * span / (uint64_t)kDegridItemCap + (uint64_t)p->NJ) + 3;
+    resident = (size_t)(p->desc.n_chan * 8 + (uint64_t)(p->alpha + 4) * p->alpha * sr +
+                        (uint64_t)(g.nu + g.nv) * sc + 2 * npix * 8 + ntot * (8 + 4 + 4) + 2 * tab_n * 4 +
+                        nact * (3 * sr + 8) + items * 16);
+    // construction also holds the radix-sort scratch (second key and value
+    // buffers, histograms, scan levels) and small host-table copies
+    const uint64_t nblocks = (ntot + kRsTile - 1) / kRsTile;
+    const uint64_t sort = ntot * 12 + 256 * nblocks * 4 * 2 + 4096;
+    const uint64_t tables = (uint64_t)(g.npix_x + g.npix_y) * 8 + 2 * 1024 * 8 + (uint64_t)6 * p->NJ * 4;
+    peak = resident + (size_t)(sort + tables);
+}
+
+// w range and number of selected visibilities (one reduction on the
+// device, read back synchronously on the plan's stream).  scale: device
+// [n_chan] freq / c.
+int plan_wrange(const wg_plan_desc &d, DevMem &mem, const double *scale, int do_w, hipStream_t st,
+                int64_t &n_active, double &wmin, double &wmax) {
+    const int64_t n_total = d.n_rows * d.n_chan;
+    unsigned long long *red = (unsigned long long *)mem.get(3 * sizeof(unsigned long long));
+    if (!red) return WG_ENOMEM;
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_wrange_init, dim3(1), dim3(64), 0, st, red);
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_wrange, dim3((unsigned)grid_blocks(n_total, 256, 4096)), dim3(256), 0, st, d.uvw,
+                           scale, d.mask, d.n_rows, d.n_chan, do_w, red);
+    unsigned long long hred[3] = {~0ull, 0ull, 0ull};
+    int rc = WG_OK;
+    if (!hip_ok(hipGetLastError(), "k_wrange")) rc = WG_EHIP;
+    if (rc == WG_OK && n_total > 0 &&
+        (!hip_ok(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, st), "w range copy") ||
+         !hip_ok(hipStreamSynchronize(st), "w range sync")))
+        rc = WG_EHIP;
+    mem.put(red);
+    if (rc != WG_OK) return rc;
+    n_active = (int64_t)hred[2];
+    if (do_w && n_active > 0) {
+        std::memcpy(&wmin, &hred[0], sizeof(double));
+        std::memcpy(&wmax, &hred[1], sizeof(double));
+    } else {
+        wmin = wmax = 0.0;
+    }
+    return WG_OK;
+}
+
+// Channel scale freq / c, computed on the host (one IEEE division) and
+// uploaded; the frequencies are checked to be positive.
+int plan_scale(const wg_plan_desc &d, DevMem &mem, hipStream_t st, double *&scale_dev) {
     std::vector<double> freq(d.n_chan), scale(d.n_chan);
     HIP_TRY(hipMemcpyAsync(freq.data(), d.freq, d.n_chan * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -420,32 +441,55 @@ int plan_build(wg_plan *p) {
         if (!(freq[c] > 0.0)) return WG_EINVAL;
         scale[c] = freq[c] / kC;
     }
-    p->scale = (double *)p->mem.get(d.n_chan * sizeof(double));
-    if (!p->scale) return WG_ENOMEM;
-    HIP_TRY(hipMemcpy(p->scale, scale.data(), d.n_chan * sizeof(double), hipMemcpyHostToDevice));
+    scale_dev = (double *)mem.get(d.n_chan * sizeof(double));
+    if (!scale_dev) return WG_ENOMEM;
+    HIP_TRY(hipMemcpyAsync(scale_dev, scale.data(), d.n_chan * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // the host vector must outlive the copy
+    return WG_OK;
+}
 
-    // w range and number of selected visibilities
-    unsigned long long *red = (unsigned long long *)p->mem.get(3 * sizeof(unsigned long long));
-    if (!red) return WG_ENOMEM;
-    unsigned long long init[3] = {~0ull, 0ull, 0ull};
-    HIP_TRY(hipMemcpyAsync(red, init, sizeof(init), hipMemcpyHostToDevice, st));
-    if (p->n_total > 0)
-        hipLaunchKernelGGL(k_wrange, dim3((unsigned)grid_blocks(p->n_total, 256, 4096)), dim3(256), 0, st, d.uvw,
-                           p->scale, d.mask, d.n_rows, d.n_chan, p->do_w, red);
-    LAUNCH_CHECK("k_wrange");
-    unsigned long long hred[3];
-    HIP_TRY(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    p->mem.put(red);
-    p->n_active = (int64_t)hred[2];
-    if (p->do_w && p->n_active > 0) {
-        std::memcpy(&p->wmin, &hred[0], sizeof(double));
-        std::memcpy(&p->wmax, &hred[1], sizeof(double));
-    } else {
-        p->wmin = p->wmax = 0.0;
-    }
+// Form of the u-axis FFT passes.  The split (four-step) form needs: the
+// fused row passes' register share of S rows (S * V values a thread, V =
+// image columns per thread of a 1024-thread workgroup: at most 32 complex
+// values in FP32, 16 in FP64), N1 = N_u / S of at least two FFT passes, and
+// a column block Q >= 8 whose N1-point transforms fit 48 KB of LDS with the
+// batch sums.  Otherwise the full-length column passes run.
+void plan_split(wg_plan *p) {
+    const Geom &g = p->g;
+    p->split_S = p->split_V = p->split_Q = 0;
+    if (p->desc.fft_path != 2) return;
+    const size_t sc = p->precision == WG_F32 ? 8 : 16;
+    const int V = (g.npix_y + kSplitThreads - 1) / kSplitThreads;
+    const int cap = p->precision == WG_F32 ? 32 : 16;
+    int S = 0;
+    for (int s : {16, 8, 4})
+        if (s * (V <= 1 ? 1 : V <= 2 ? 2 : 4) <= cap && V <= 4) {
+            S = s;
+            break;
+        }
+    if (!S || g.nu % S || g.nv > kSplitThreads * 12) return;
+    const int N1 = g.nu / S;
+    FftDesc f1;
+    make_fft_desc(N1, f1);
+    if (f1.npass < 2) return;
+    int Q = 0;
+    for (int q = 64; q >= 8; q /= 2)
+        if ((size_t)fft_lds_len(N1) * q * sc + (size_t)N1 * q * (sc / 2) <= 48 * 1024 && N1 * q <= 256 * kFftMaxC) {
+            Q = q;
+            break;
+        }
+    if (!Q) return;
+    p->split_S = S;
+    p->split_V = V <= 1 ? 1 : V <= 2 ? 2 : 4;
+    p->split_Q = Q;
+    p->fft_u1 = f1;
+}
 
-    // kernel choice
+// Host planning once the w range and the active count are known: kernel
+// choice (Sect. 4.1), polynomial degree (Sect. 4.2), grid and plane geometry
+// (Sect. 2), batching and FFT descriptors.  No device work.
+int plan_host(wg_plan *p) {
+    const wg_plan_desc &d = p->desc;
     if (d.alpha) {
         p->alpha = d.alpha;
         p->sigma = d.sigma;
@@ -462,6 +506,14 @@ int plan_build(wg_plan *p) {
     p->eps_k = row->eps;
     p->degree = choose_degree(p->alpha, p->beta, p->mu, p->eps_k, d.precision);
     if (p->degree > p->alpha + 3) return WG_EUNSUPPORTED;   // the kernels' LDS table holds alpha + 4 rows
+    {
+        std::vector<double> c;
+        kernel_poly(p->alpha, p->beta, p->mu, p->degree, c);
+        p->poly_err = kernel_poly_max_error(p->alpha, p->beta, p->mu, p->degree, c);
+    }
+    p->amp = rounding_amplification(p->alpha, p->sigma, p->do_w, d.npix_x, d.npix_y, d.pixsize_x, d.pixsize_y);
+    p->round_err = rounding_error(p->alpha, p->sigma, d.precision, p->do_w, d.npix_x, d.npix_y, d.pixsize_x,
+                                  d.pixsize_y);
 
     // geometry (Sect. 2)
     Geom &g = p->g;
@@ -507,10 +559,29 @@ int plan_build(wg_plan *p) {
     const int max_slots = d.precision == WG_F32 ? 8 : 4;
     p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, p->alpha) : p->alpha;
     p->P = std::min(std::min(p->P, max_slots), g.nw);
-    (void)sc;
     p->NJ = (g.nw + p->P - 1) / p->P;
     make_fft_desc(g.nu, p->fft_u);
     make_fft_desc(g.nv, p->fft_v);
+    plan_split(p);
+    return WG_OK;
+}
+
+int plan_build(wg_plan *p) {
+    const wg_plan_desc &d = p->desc;
+    hipStream_t st = p->stream;
+    HIP_TRY(hipGetDevice(&p->device));
+    p->precision = d.precision;
+    p->do_w = d.do_wgridding ? 1 : 0;
+    p->n_total = d.n_rows * d.n_chan;
+    int rc = plan_scale(d, p->mem, st, p->scale);
+    if (rc != WG_OK) return rc;
+    rc = plan_wrange(d, p->mem, p->scale, p->do_w, st, p->n_active, p->wmin, p->wmax);
+    if (rc != WG_OK) return rc;
+    rc = plan_host(p);
+    if (rc != WG_OK) return rc;
+    const Geom &g = p->g;
+    const size_t sc = d.precision == WG_F32 ? 8 : 16;
+    const size_t sr = sc / 2;
 
     // host tables: polynomial, psi on the pixel axes, quadrature nodes, twiddles
     std::vector<double> coef_id;
@@ -524,11 +595,12 @@ int plan_build(wg_plan *p) {
     std::vector<double> psix(d.npix_x), psiy(d.npix_y);
     for (int i = 0; i < d.npix_x; ++i) psix[i] = psi_eval((double)(i - d.npix_x / 2) / g.nu, qt, qw);
     for (int i = 0; i < d.npix_y; ++i) psiy[i] = psi_eval((double)(i - d.npix_y / 2) / g.nv, qt, qw);
-    std::vector<double> tur, tui, tvr, tvi;
+    std::vector<double> tur, tui, tvr, tvi, t1r, t1i;
     twiddles(g.nu, tur, tui);
     twiddles(g.nv, tvr, tvi);
-    int rc = d.precision == WG_F32 ? build_plan_tables<float>(p, coefd, tur, tui, tvr, tvi)
-                                   : build_plan_tables<double>(p, coefd, tur, tui, tvr, tvi);
+    if (p->split_S) twiddles(g.nu / p->split_S, t1r, t1i);
+    rc = d.precision == WG_F32 ? build_plan_tables<float>(p, coefd, tur, tui, tvr, tvi, t1r, t1i)
+                               : build_plan_tables<double>(p, coefd, tur, tui, tvr, tvi, t1r, t1i);
     if (rc != WG_OK) return rc;
 
     // correction factors
@@ -540,10 +612,11 @@ int plan_build(wg_plan *p) {
     double *dqt = (double *)p->mem.get(qt.size() * sizeof(double));
     double *dqw = (double *)p->mem.get(qw.size() * sizeof(double));
     if (!p->nm1 || !p->corr || !dpx || !dpy || !dqt || !dqw) return WG_ENOMEM;
-    HIP_TRY(hipMemcpy(dpx, psix.data(), psix.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dpy, psiy.data(), psiy.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dqt, qt.data(), qt.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dqw, qw.data(), qw.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(dpx, psix.data(), psix.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dpy, psiy.data(), psiy.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dqt, qt.data(), qt.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dqw, qw.data(), qw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // host vectors live until here
     hipLaunchKernelGGL(k_corr, dim3((unsigned)grid_blocks(npix, 256, 1 << 20)), dim3(256), 0, st, d.npix_x,
                        d.npix_y, d.pixsize_x, d.pixsize_y, p->do_w, g.dw, dpx, dpy, dqt, dqw, (int)qt.size(),
                        p->nm1, p->corr);
@@ -612,92 +685,22 @@ int plan_build(wg_plan *p) {
     p->mem.put(dqt);
     p->mem.put(dqw);
 
-    // workspace layout
-    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t off = 0;
-    p->off_G = off;
-    off = align(off + (size_t)p->P * g.nu * g.nv * sc);
-    p->off_T = off;
-    off = align(off + (size_t)p->P * std::max((size_t)g.nu * d.npix_y, (size_t)d.npix_x * g.nv) * sc);
-    p->off_acc = off;
-    off = align(off + (size_t)npix * sr);
-    p->off_itil = off;
-    off = align(off + (size_t)npix * sr);
-    p->off_vacc = off;
-    off = align(off + (size_t)std::max<int64_t>(p->n_active, 1) * sc);
-    p->off_part = off;
-    off = align(off + (size_t)p->max_slots * p->P * kTile * kTile * sc);
-    p->ws_bytes = off;
+    plan_layout(p, p->max_slots);
     return WG_OK;
 }
 
 // ---- apply ------------------------------------------------------------------
 
-// blocks of a vis-kernel launch: the extra items (padded to a multiple of
-// 8) and then one block per tile (padded likewise)
-inline unsigned item_blocks(const wg_plan *p, uint32_t n_extra) {
-    const int nt = p->g.ntu * p->g.ntv;
-    return (unsigned)(((n_extra + 7) & ~7u) + (((unsigned)nt + 7) & ~7u));
-}
-
-template <typename R, int ALPHA> struct Launch {
-    template <int PS>
-    static void grid_ps(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
-        const size_t lds = GridStage<R, ALPHA, PS>::bytes;
-        hipLaunchKernelGGL((k_grid<R, ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
-                           p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
-    }
-    template <int PS>
-    static void grid_mx(const wg_plan *p, const VisArgs<float> &va, int J, float2 *G, float2 *part,
-                        hipStream_t st) {
-        const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
-        const size_t lds = GridStageMx<ALPHA>::bytes;
-        hipLaunchKernelGGL((k_grid_mx<ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
-                           p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
-    }
-    static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        if constexpr (sizeof(R) == 4) {      // FP32: matrix cores
-            if (p->P > 4)
-                grid_mx<8>(p, va, J, G, part, st);
-            else
-                grid_mx<4>(p, va, J, G, part, st);
-        } else {
-            grid_ps<4>(p, va, J, G, part, st);
-        }
-        // partial tiles of split items, added in item order
-        const uint32_t nr = p->xr_off[J + 1] - p->xr_off[J];
-        if (nr > 0) {
-            const int np = std::min(p->P, p->g.nw - J * p->P);
-            hipLaunchKernelGGL(k_grid_reduce<R>, dim3(nr), dim3(kTileArea), 0, st, p->xr + p->xr_off[J], (int)nr,
-                               p->P, np, p->g, (const Cx<R> *)part, G);
-        }
-    }
-    static void degrid(const wg_plan *p, const VisArgs<R> &va, int J, const Cx<R> *G, Cx<R> *vacc,
-                       hipStream_t st) {
-        const uint32_t ne = p->xd_off[J + 1] - p->xd_off[J];
-        const int W = kTileCells + ALPHA - 1;
-        // planes staged at a time: about 20 KiB of tile + halo, so that
-        // eight workgroups (32 waves) share a CU; the kernel values are
-        // evaluated once per staged group (measured: 4 planes of 8 at a time
-        // beat all 8 at once, 0.49 vs 0.57 ms)
-        const int pd = std::max(1, std::min(p->P, (int)(20 * 1024 / ((size_t)W * W * sizeof(Cx<R>)))));
-        const size_t lds = (((size_t)pd * W * W * sizeof(Cx<R>) + 15) & ~(size_t)15) + kCoefBytes<R, ALPHA>;
-        hipLaunchKernelGGL((k_degrid<R, ALPHA>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J, pd,
-                           p->xd + p->xd_off[J], (int)ne, kDegridItemCap, G, vacc);
-    }
-};
-
 template <typename R>
 void launch_vis_kernel(bool gridding, const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *vacc,
                        Cx<R> *part, hipStream_t st) {
     switch (p->alpha) {
-#define CASE(A)                                                              \
-    case A:                                                                  \
-        if (gridding) Launch<R, A>::grid(p, va, J, G, part, st);             \
-        else Launch<R, A>::degrid(p, va, J, G, vacc, st);                    \
+#define CASE(A)                                                          \
+    case A:                                                              \
+        launch_vis<R, A>(gridding, p, va, J, G, vacc, part, st);         \
         break;
-        CASE(4) CASE(7) CASE(8) CASE(12) CASE(16)
+        CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15)
+        CASE(16)
 #undef CASE
         default: break;
     }
@@ -820,13 +823,24 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                     ProfScope ps(WG_KIND_GRID, st);
                     launch_vis_kernel<R>(true, p, va, J, G, nullptr, part, st);
                 }
-                {
-                    ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
-                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
-                }
-                {
-                    ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
-                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                if (p->split_S) {
+                    {
+                        ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
+                        split_rows_grid<R>(p, G, T, np, st);
+                    }
+                    {
+                        ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
+                        split_cols_grid<R>(p, T, acc, j_lo, np, st);
+                    }
+                } else {
+                    {
+                        ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
+                        DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
+                    }
+                    {
+                        ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
+                        DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                    }
                 }
             }
         }
@@ -855,13 +869,24 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
-                {
-                    ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
-                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
-                }
-                {
-                    ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
-                    DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
+                if (p->split_S) {
+                    {
+                        ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
+                        split_cols_degrid<R>(p, itil, T, j_lo, np, st);
+                    }
+                    {
+                        ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
+                        split_rows_degrid<R>(p, T, G, np, st);
+                    }
+                } else {
+                    {
+                        ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
+                        DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
+                    }
+                    {
+                        ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
+                        DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
+                    }
                 }
                 {
                     ProfScope ps(WG_KIND_DEGRID, st);
@@ -911,19 +936,7 @@ int wg_plan_create(const wg_plan_desc *desc, wg_plan **out) {
 
 int wg_plan_destroy(wg_plan *p) {
     if (!p) return WG_OK;
-    (void)hipStreamSynchronize(p->stream);
-    p->mem.put(p->scale);
-    p->mem.put(p->coef);
-    p->mem.put(p->tw_u);
-    p->mem.put(p->tw_v);
-    p->mem.put(p->nm1);
-    p->mem.put(p->corr);
-    p->mem.put(p->keys);
-    p->mem.put(p->order);
-    p->mem.put(p->tab_lo);
-    p->mem.put(p->tab_hi);
-    p->mem.put(p->zc);
-    p->mem.put(p->anc);
+    p->mem.release_all();
     delete p;
     return WG_OK;
 }
@@ -983,7 +996,42 @@ int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
     info->workspace_bytes = p->ws_bytes;
     info->extra_items_grid = p->xg_off.empty() ? 0 : p->xg_off.back();
     info->extra_items_degrid = p->xd_off.empty() ? 0 : p->xd_off.back();
+    info->rounding_error = p->round_err;
+    info->amplification = p->amp;
+    info->poly_error = p->poly_err;
+    info->fft_split = p->split_S;
     return WG_OK;
+}
+
+int wg_plan_estimate(const wg_plan_desc *desc, size_t *plan_bytes, size_t *peak_bytes, size_t *workspace_bytes) {
+    int rc = validate(desc);
+    if (rc != WG_OK) return rc;
+    wg_plan *p = new (std::nothrow) wg_plan();
+    if (!p) return WG_ENOMEM;
+    p->desc = *desc;
+    p->stream = (hipStream_t)desc->stream;
+    p->mem.alloc = desc->alloc;
+    p->mem.free = desc->free;
+    p->mem.ctx = desc->alloc_ctx;
+    p->precision = desc->precision;
+    p->do_w = desc->do_wgridding ? 1 : 0;
+    p->n_total = desc->n_rows * desc->n_chan;
+    rc = plan_scale(*desc, p->mem, p->stream, p->scale);
+    if (rc == WG_OK) rc = plan_wrange(*desc, p->mem, p->scale, p->do_w, p->stream, p->n_active, p->wmin, p->wmax);
+    if (rc == WG_OK) rc = plan_host(p);
+    if (rc == WG_OK) {
+        size_t res = 0, peak = 0;
+        plan_footprint(p, res, peak);
+        // partial-tile slots of the gridder: at most one per item beyond the
+        // first of a tile, and a batch deals at most 4 n_active visibility visits
+        const int64_t slots = 4 * std::max<int64_t>(p->n_active, 1) / kGridItemCap + 1;
+        const size_t ws = plan_layout(p, slots);
+        if (plan_bytes) *plan_bytes = res;
+        if (peak_bytes) *peak_bytes = peak;
+        if (workspace_bytes) *workspace_bytes = ws;
+    }
+    delete p;   // releases the temporaries
+    return rc;
 }
 
 size_t wg_workspace_bytes(const wg_plan *p) { return p ? p->ws_bytes : 0; }
@@ -1096,6 +1144,36 @@ int wg_kernel_poly(int alpha, double sigma, int precision, double *coeffs, int c
         int n = std::min<int>(cap, (int)c.size());
         for (int i = 0; i < n; ++i) coeffs[i] = c[i];
     }
+    return WG_OK;
+}
+
+int wg_kernel_search(int alpha, double sigma, double *beta, double *mu, double *eps) {
+    if (alpha < 2 || alpha > 16 || !(sigma > 1.0 && sigma <= 4.0) || !beta || !mu) return WG_EINVAL;
+    double b = *beta, m = *mu;
+    const double e = kernel_search(alpha, sigma, &b, &m);
+    *beta = b;
+    *mu = m;
+    if (eps) *eps = e;
+    return WG_OK;
+}
+
+int wg_kernel_map_error(int alpha, double sigma, double beta, double mu, double *eps) {
+    if (alpha < 2 || alpha > 16 || !(sigma > 1.0 && sigma <= 4.0) || !(beta > 0.0) || !(mu > 0.0) || !eps)
+        return WG_EINVAL;
+    *eps = map_error_sup(alpha, sigma, beta, mu);
+    return WG_OK;
+}
+
+int wg_kernel_table(int index, int *alpha, double *sigma, double *eps, double *beta, double *mu, int *printed) {
+    const std::vector<KernelRow> &t = planner_table();
+    if (index < 0 || index >= (int)t.size()) return WG_EINVAL;
+    const KernelRow &r = t[index];
+    if (alpha) *alpha = r.alpha;
+    if (sigma) *sigma = r.sigma;
+    if (eps) *eps = r.eps;
+    if (beta) *beta = r.beta;
+    if (mu) *mu = r.mu;
+    if (printed) *printed = is_printed(r.alpha, r.sigma) ? 1 : 0;
     return WG_OK;
 }
 

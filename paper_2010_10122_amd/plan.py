@@ -37,6 +37,56 @@ def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+class _TorchAllocator:
+    """Device-memory callbacks of the C ABI served by PyTorch's caching
+    allocator, so that plan memory is pooled with the rest of the program's.
+    Blocks are associated with the plan's construction stream; the ctypes
+    callables must outlive the plan."""
+
+    def __init__(self, device, stream):
+        self.device = device
+        self.stream = stream
+        self.c_alloc = _lib._alloc_fn(self._alloc)
+        self.c_free = _lib._free_fn(self._free)
+
+    def _alloc(self, ctx, nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:          # out of memory: the library reports WG_ENOMEM
+            return None
+
+    def _free(self, ctx, ptr):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:          # interpreter shutdown
+            pass
+
+
+def _fill_desc(d, uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision, do_wgridding,
+               alpha, sigma, planes_per_batch, stream, allocator, fft_path=0):
+    d.uvw = uvw.data_ptr()
+    d.freq = freq.data_ptr()
+    d.mask = mask.data_ptr() if mask is not None else None
+    d.n_rows = int(uvw.shape[0])
+    d.n_chan = int(freq.shape[0])
+    d.npix_x = int(npix_x)
+    d.npix_y = int(npix_y)
+    d.pixsize_x = float(pixsize_x)
+    d.pixsize_y = float(pixsize_y)
+    d.epsilon = float(epsilon)
+    d.precision = precision
+    d.do_wgridding = 1 if do_wgridding else 0
+    d.alpha = int(alpha or 0)
+    d.sigma = float(sigma or 0.0)
+    d.planes_per_batch = int(planes_per_batch or 0)
+    d.fft_path = {None: 0, 0: 0, "auto": 0, 1: 1, "columns": 1, 2: 2, "split": 2}[fft_path]
+    d.stream = _stream_handle(stream).value
+    if allocator is not None:
+        d.alloc = allocator.c_alloc
+        d.free = allocator.c_free
+    return d
+
+
 class Plan:
     """A w-gridding operator for fixed coordinates and image geometry.
 
@@ -44,12 +94,14 @@ class Plan:
     optional mask [n_rows, n_chan] uint8 must be CUDA tensors; they are kept
     alive by the plan and must not be modified while it is in use.
     precision: "f32" (epsilon >= 1e-5) or "f64".
-    alpha/sigma force a printed Appendix-A kernel; planes_per_batch forces
-    the w-plane batch size.
+    alpha/sigma force a kernel of the planner's table (wg_kernel_table);
+    planes_per_batch forces the w-plane batch size; fft_path "columns" or
+    "split" forces the form of the u-axis FFT passes.
     """
 
     def __init__(self, uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision="f32",
-                 do_wgridding=True, mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None):
+                 do_wgridding=True, mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None,
+                 torch_allocator=True, fft_path=None):
         lib = _lib.load()
         for name, t, dt in (("uvw", uvw, torch.float64), ("freq", freq, torch.float64)):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
@@ -66,23 +118,14 @@ class Plan:
         self.n_rows, self.n_chan = int(uvw.shape[0]), int(freq.shape[0])
         self.npix_x, self.npix_y = int(npix_x), int(npix_y)
         self.device = uvw.device
-        d = _lib.PlanDesc()
-        d.uvw = uvw.data_ptr()
-        d.freq = freq.data_ptr()
-        d.mask = mask.data_ptr() if mask is not None else None
-        d.n_rows = self.n_rows
-        d.n_chan = self.n_chan
-        d.npix_x = self.npix_x
-        d.npix_y = self.npix_y
-        d.pixsize_x = float(pixsize_x)
-        d.pixsize_y = float(pixsize_y)
-        d.epsilon = float(epsilon)
-        d.precision = self.precision
-        d.do_wgridding = 1 if do_wgridding else 0
-        d.alpha = int(alpha or 0)
-        d.sigma = float(sigma or 0.0)
-        d.planes_per_batch = int(planes_per_batch or 0)
-        d.stream = _stream_handle(stream).value
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        # device memory of the plan comes from PyTorch's caching allocator
+        # (torch_allocator=False: hipMalloc / hipFree inside the library)
+        self._alloc = _TorchAllocator(self.device, stream) if torch_allocator else None
+        d = _fill_desc(_lib.PlanDesc(), uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon,
+                       self.precision, do_wgridding, alpha, sigma, planes_per_batch, stream, self._alloc,
+                       fft_path)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             rc = lib.wg_plan_create(ctypes.byref(d), ctypes.byref(handle))
@@ -97,7 +140,28 @@ class Plan:
         _lib.check(self._lib.wg_plan_info(self._h, ctypes.byref(inf)), "wg_plan_info")
         return {name: getattr(inf, name) for name, _ in _lib.PlanInfo._fields_}
 
+    @staticmethod
+    def estimate(uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision="f32", do_wgridding=True,
+                 mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None):
+        """Device bytes (plan, peak during construction, workspace bound) of the
+        plan these arguments would build, without building it
+        (``wg_plan_estimate``)."""
+        lib = _lib.load()
+        dev = uvw.device
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        alloc = _TorchAllocator(dev, stream)
+        d = _fill_desc(_lib.PlanDesc(), uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon,
+                       _precision_of(precision), do_wgridding, alpha, sigma, planes_per_batch, stream, alloc)
+        pb, pk, wb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        with torch.cuda.device(dev):
+            rc = lib.wg_plan_estimate(ctypes.byref(d), ctypes.byref(pb), ctypes.byref(pk), ctypes.byref(wb))
+        _lib.check(rc, "wg_plan_estimate")
+        return {"plan_bytes": pb.value, "peak_bytes": pk.value, "workspace_bytes": wb.value}
+
     def close(self):
+        """Release the plan's device memory.  No apply call on the plan may be
+        running on any stream."""
         if getattr(self, "_h", None):
             self._lib.wg_plan_destroy(self._h)
             self._h = None
@@ -109,6 +173,7 @@ class Plan:
             pass
 
     def _workspace(self, workspace):
+        # (called under the launch stream, so the block belongs to that stream)
         if workspace is None:
             return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
         if workspace.numel() * workspace.element_size() < self.workspace_bytes or not workspace.is_cuda:
@@ -130,11 +195,13 @@ class Plan:
             raise TypeError(f"dirty must be a contiguous CUDA {self.real_dtype} tensor "
                             f"[{self.npix_x}, {self.npix_y}]")
         wgt = self._check_wgt(wgt)
-        if out is None:
-            out = torch.empty((self.n_rows, self.n_chan), dtype=self.complex_dtype, device=self.device)
-        ws = self._workspace(workspace)
-        rc = self._lib.wg_degrid(self._h, _dev_ptr(dirty), _dev_ptr(wgt), _dev_ptr(out), _dev_ptr(ws),
-                                 ws.numel(), _stream_handle(stream))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(st):
+            if out is None:
+                out = torch.empty((self.n_rows, self.n_chan), dtype=self.complex_dtype, device=self.device)
+            ws = self._workspace(workspace)
+            rc = self._lib.wg_degrid(self._h, _dev_ptr(dirty), _dev_ptr(wgt), _dev_ptr(out), _dev_ptr(ws),
+                                     ws.numel(), _stream_handle(st))
         _lib.check(rc, "wg_degrid")
         return out
 
@@ -145,11 +212,13 @@ class Plan:
             raise TypeError(f"vis must be a contiguous CUDA {self.complex_dtype} tensor "
                             f"[{self.n_rows}, {self.n_chan}]")
         wgt = self._check_wgt(wgt)
-        if out is None:
-            out = torch.empty((self.npix_x, self.npix_y), dtype=self.real_dtype, device=self.device)
-        ws = self._workspace(workspace)
-        rc = self._lib.wg_grid(self._h, _dev_ptr(vis), _dev_ptr(wgt), _dev_ptr(out), _dev_ptr(ws),
-                               ws.numel(), _stream_handle(stream))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(st):
+            if out is None:
+                out = torch.empty((self.npix_x, self.npix_y), dtype=self.real_dtype, device=self.device)
+            ws = self._workspace(workspace)
+            rc = self._lib.wg_grid(self._h, _dev_ptr(vis), _dev_ptr(wgt), _dev_ptr(out), _dev_ptr(ws),
+                                   ws.numel(), _stream_handle(st))
         _lib.check(rc, "wg_grid")
         return out
 
@@ -251,3 +320,38 @@ def kernel_psi(alpha, sigma, k):
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "wg_kernel_psi")
     return out
+
+
+def kernel_search(alpha, sigma, start=None):
+    """(beta, mu, eps): the sup-norm search of the map error function over the
+    modified ES kernel's parameters (Sect. 3.2, eq. maperror); ``start`` an
+    optional extra starting point (beta, mu)."""
+    b = ctypes.c_double(start[0] if start else 0.0)
+    m = ctypes.c_double(start[1] if start else 0.0)
+    e = ctypes.c_double()
+    _lib.check(_lib.load().wg_kernel_search(int(alpha), float(sigma), ctypes.byref(b), ctypes.byref(m),
+                                            ctypes.byref(e)), "wg_kernel_search")
+    return b.value, m.value, e.value
+
+
+def kernel_map_error(alpha, sigma, beta, mu):
+    """Supremum over the retained band of the map error function (eq. maperror)."""
+    e = ctypes.c_double()
+    _lib.check(_lib.load().wg_kernel_map_error(int(alpha), float(sigma), float(beta), float(mu), ctypes.byref(e)),
+               "wg_kernel_map_error")
+    return e.value
+
+
+def kernel_table():
+    """Rows (alpha, sigma, eps, beta, mu, printed) of the planner's kernel table."""
+    lib = _lib.load()
+    rows = []
+    i = 0
+    while True:
+        a, s, e, b, m, pr = (ctypes.c_int(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double(),
+                             ctypes.c_double(), ctypes.c_int())
+        if lib.wg_kernel_table(i, ctypes.byref(a), ctypes.byref(s), ctypes.byref(e), ctypes.byref(b), ctypes.byref(m),
+                               ctypes.byref(pr)) != _lib.WG_OK:
+            return rows
+        rows.append((a.value, s.value, e.value, b.value, m.value, bool(pr.value)))
+        i += 1

@@ -192,3 +192,71 @@ def serving_requests(seed=4, count=32, sizes=(512, 1024, 2048, 4096), nvis_range
                         direction="degrid" if rng.random() < 0.5 else "grid",
                         seed=int(rng.integers(0, 2 ** 31))))
     return base, out
+
+
+def meerkat_like(seed=6, n_dumps=436, n_chan=2048, npix=4096, fov_deg=1.6, n_src=1000, target_vis=470e6,
+                 with_mask=True):
+    """Workload shaped like the benchmark set of Sect. 6 (a MeerKAT L-band
+    observation that is not available here; every number below is a
+    reading): 61 antennas, autocorrelations included, so 1891 baselines per
+    dump; 436 dumps over 11 h, which gives the 824,476 rows of that set;
+    2048 channels over 856-1712 MHz; a 4096^2 image over 1.6 deg.
+
+    Antennas: 61 of them with radii 4 km * U^2 (a dense core, longest
+    baselines near 8 km), uniform position angles; latitude -30.7 deg,
+    phase centre at declination -30 deg.  Flags (mask = 0): all
+    autocorrelations, six channel bands typical of L-band interference
+    (band edges, mobile, navigation and satellite bands), and blocks of
+    64 channels x 1 row with a flagging probability chosen so that about
+    ``target_vis`` visibilities remain (470 million in Sect. 6).  Image:
+    ``n_src`` point sources with log-normal fluxes."""
+    rng = np.random.default_rng(seed)
+    n_ant = 61
+    r = 4000.0 * rng.random(n_ant) ** 2
+    th = 2.0 * np.pi * rng.random(n_ant)
+    ant = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    i, j = np.triu_indices(n_ant, k=0)                   # with autocorrelations
+    de = ant[j, 0] - ant[i, 0]
+    dn = ant[j, 1] - ant[i, 1]
+    lat, dec = -30.7 * DEG, -30.0 * DEG
+    lx, ly, lz = -math.sin(lat) * dn, de, math.cos(lat) * dn
+    half = 0.5 * 11.0 * 15.0 * DEG
+    ha = np.linspace(-half, half, n_dumps)
+    sh, ch = np.sin(ha)[:, None], np.cos(ha)[:, None]
+    u = sh * lx[None, :] + ch * ly[None, :]
+    v = -math.sin(dec) * ch * lx[None, :] + math.sin(dec) * sh * ly[None, :] + math.cos(dec) * lz[None, :]
+    w = math.cos(dec) * ch * lx[None, :] - math.cos(dec) * sh * ly[None, :] + math.sin(dec) * lz[None, :]
+    uvw = np.stack([u.ravel(), v.ravel(), w.ravel()], axis=1)
+    auto = np.tile(i == j, n_dumps)
+    freq = np.linspace(856e6, 1712e6, n_chan, endpoint=False) + 0.5 * 856e6 / n_chan
+    pix = fov_deg * DEG / npix
+    img = point_sources(rng, npix, npix, n_src)
+    out = dict(uvw=uvw, freq=freq, npix_x=npix, npix_y=npix, pixsize_x=pix, pixsize_y=pix, dirty=img,
+               name=f"meerkat-like-{npix}^2-{uvw.shape[0]}x{n_chan}")
+    if with_mask:
+        bad = np.zeros(n_chan, dtype=bool)
+        for lo, hi in ((856e6, 880e6), (925e6, 960e6), (1164e6, 1300e6), (1525e6, 1630e6), (1690e6, 1712e6),
+                       (1080e6, 1095e6)):
+            bad |= (freq >= lo) & (freq < hi)
+        nblk = (n_chan + 63) // 64
+        rows_ok = ~auto
+        n_ok = int(rows_ok.sum()) * int((~bad).sum())
+        keep = min(1.0, target_vis / n_ok)
+        blk = rng.random((uvw.shape[0], nblk)) < keep
+        mask = np.repeat(blk, 64, axis=1)[:, :n_chan] & (~bad)[None, :] & rows_ok[:, None]
+        out["mask"] = mask.view(np.uint8)
+    return out
+
+
+def flatten_channels(uvw, freq, mask, f0=None):
+    """The 'flattened' form of multi-channel data used in Sect. 6.2: one
+    row per selected visibility, its uvw scaled to a single reference
+    frequency f0 (default: the first channel), so that the effective
+    coordinates uvw * f / c are unchanged.  Returns (uvw_flat [n, 3],
+    freq [1], linear indices r * n_chan + c of the selected visibilities)."""
+    f0 = float(freq[0]) if f0 is None else float(f0)
+    idx = np.flatnonzero(np.asarray(mask).reshape(-1))
+    r = idx // len(freq)
+    c = idx - r * len(freq)
+    uvw_flat = uvw[r] * (np.asarray(freq)[c] / f0)[:, None]
+    return uvw_flat, np.array([f0]), idx

@@ -46,3 +46,60 @@ def oracle_plan_from(info, case, mask=None):
     return P.make_plan(case["uvw"], case["freq"], case["npix_x"], case["npix_y"], case["pixsize_x"],
                        case["pixsize_y"], info["alpha"], info["sigma"], do_wgridding=bool(info["do_wgridding"]),
                        mask=mask)
+
+
+def check_binning_full(case, plan, torch, mask=None, chunk_rows=1 << 20):
+    """Bit-exact binning at any size: the plan's geometry equals the oracle's
+    plan for the same (alpha, sigma), and its sorted index (keys, order)
+    equals the stable sort of the oracle's binning spec.
+
+    The sorted order is checked through properties that make it unique:
+    the keys ascend, equal keys keep ascending linear indices (stability),
+    and ``order`` is a permutation of the selected visibilities.  The key
+    of every visibility is then compared with the oracle's, computed on the
+    host in row chunks so that memory stays bounded.  Returns the number of
+    visibilities compared."""
+    import numpy as np
+    from oracle import plan as P
+    info = plan.info
+    pl = oracle_plan_from(info, case, mask)
+    assert (info["nu"], info["nv"], info["nw"]) == (pl["nu"], pl["nv"], pl["nw"])
+    assert info["dw"] == pl["dw"] and info["w0"] == pl["w0"]
+    assert info["wmin"] == pl["wmin"] and info["wmax"] == pl["wmax"]
+    keys, order = plan.index()
+    n_total = case["uvw"].shape[0] * len(case["freq"])
+    n = int(info["n_vis"])
+    assert keys.numel() == n and order.numel() == n
+    if n == 0:
+        return 0
+    # ascending keys; stable ties
+    assert bool(torch.all(keys[1:] >= keys[:-1]))
+    tie = keys[1:] == keys[:-1]
+    o = order.to(torch.int64)
+    assert bool(torch.all(o[1:][tie] > o[:-1][tie]))
+    # a permutation of the selected visibilities (each exactly once)
+    cnt = torch.zeros(n_total, dtype=torch.int32, device=keys.device)
+    cnt.index_add_(0, o, torch.ones_like(order))
+    if mask is None:
+        assert bool(torch.all(cnt == 1))
+    else:
+        sel = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8).ravel() != 0).to(keys.device)
+        assert bool(torch.all(cnt == sel.to(torch.int32)))
+    del cnt, tie
+    # key of each visibility in the caller's (row, channel) order
+    key_in = torch.full((n_total,), -1, dtype=torch.int64, device=keys.device)
+    key_in[o] = keys
+    del o
+    nrow, nchan = case["uvw"].shape[0], len(case["freq"])
+    checked = 0
+    for r0 in range(0, nrow, chunk_rows):
+        r1 = min(nrow, r0 + chunk_rows)
+        mk = None if mask is None else mask[r0:r1]
+        b = P.bin_visibilities(case["uvw"][r0:r1], case["freq"], pl, mk)
+        got = key_in[r0 * nchan:r1 * nchan].cpu().numpy()
+        if mk is not None:
+            got = got[np.asarray(mk).ravel() != 0]
+        assert np.array_equal(got.astype(np.uint64), b["key"]), (r0, r1)
+        checked += len(b["key"])
+    assert checked == n
+    return checked

@@ -3,18 +3,23 @@ configuration bench.py times, on sampled outputs the direct transform (O1)
 evaluates one by one:
 
 * wide field (2048^2 over 10 deg, 92,897,280 visibilities): FP32 at
-  eps = 1e-5 and FP64 at eps = 1e-10, both directions;
+  eps = 1e-5, FP64 at eps = 1e-5 (the plain FP64 form) and at eps = 1e-10,
+  both directions;
 * large (8192^2 over 30 deg, 261,120,000 visibilities, about 12,500
   w-planes): FP32 at eps = 1e-5, both directions.
 
 Degridding is checked on random visibilities, gridding on random pixels;
-the relative L2 error of the sample must stay below eps.
+the relative L2 error of the sample must stay below eps.  Binning (Sect.
+4.3) is checked bit for bit against the oracle's binning spec on every
+visibility of both workloads.
 """
 import numpy as np
 import pytest
 
 import synth
 from oracle import o1
+
+from gpu_util import check_binning_full
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -37,7 +42,7 @@ def wide():
     return synth.wide_field()
 
 
-@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-10)])
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-5), ("f64", 1e-10)])
 def test_wide_field_sampled(dev, wide, prec, eps):
     import paper_2010_10122_amd as wg
     c = wide
@@ -67,6 +72,20 @@ def test_wide_field_sampled(dev, wide, prec, eps):
     e_grid = _rel(got_i, ref_i)
     print(f"   degrid {e_deg:.2e} (2000 vis)  grid {e_grid:.2e} (32 px)", flush=True)
     assert e_deg < eps and e_grid < eps
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-5), ("f64", 1e-10)])
+def test_wide_field_binning_bit_exact(dev, wide, prec, eps):
+    import paper_2010_10122_amd as wg
+    c = wide
+    print(f"[wide binning] {prec} eps={eps}", flush=True)
+    uvw = torch.from_numpy(c["uvw"]).to(dev)
+    freq = torch.from_numpy(c["freq"]).to(dev)
+    plan = wg.Plan(uvw, freq, c["npix_x"], c["npix_y"], c["pixsize_x"], c["pixsize_y"], eps, prec)
+    n = check_binning_full(c, plan, torch)
+    print(f"   {n} keys bit-exact (alpha={plan.info['alpha']} sigma={plan.info['sigma']} "
+          f"N={plan.info['nu']} Nw={plan.info['nw']})", flush=True)
     plan.close()
 
 
@@ -110,3 +129,10 @@ def test_large_grid_sampled(dev, large):
     e = _rel(got, ref)
     print(f"   grid {e:.2e} (16 px)", flush=True)
     assert e < 1e-5
+
+
+def test_large_binning_bit_exact(dev, large):
+    c, plan = large
+    print("[large binning]", flush=True)
+    n = check_binning_full(c, plan, torch, chunk_rows=1 << 21)
+    print(f"   {n} keys bit-exact", flush=True)

@@ -85,25 +85,37 @@ def test_binning_and_plan_bit_exact(dev, which):
 
 @pytest.mark.parametrize("alpha,sigma,prec", [(16, 1.35, "f64"), (12, 1.5, "f64"), (8, 1.45, "f32"),
                                               (7, 1.5, "f32"), (4, 2.0, "f64"), (8, 1.45, "f64"),
-                                              (12, 1.5, "f32")])
+                                              (12, 1.8, "f32"), (12, 1.6, "f32")])
 def test_same_plan_as_o2(dev, alpha, sigma, prec):
+    """The product and O2 at the same plan differ by the product's
+    polynomial kernel (Sect. 4.2) and by rounding.  The polynomial deviates
+    from phi by at most the plan's poly_error, which the degree choice keeps
+    at a fraction of eps_k (FP64) or near the FP32 evaluation floor; its
+    effect on the output stays below eps_k.  Rounding on the grid and in the
+    FFTs is magnified by the correction 1/(n Psi) (Sect. 2); the plan
+    exports that estimate (rounding_error = 1.2 ulp x the rms of
+    Psi(0)/Psi over the image).  Tolerance: max(eps_k, 2 rounding_error).
+    The FP32 plans at alpha = 12 are ones the planner accepts at eps = 1e-5
+    (sigma >= 1.6; at sigma = 1.5 the estimate is 5e-5, and the planner
+    rejects that plan in FP32)."""
     case = _case_small()
     print(f"[o2] alpha={alpha} sigma={sigma} {prec}", flush=True)
     res = run_product(case, 1e-2, prec, torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=alpha, sigma=sigma)
-    pl = oracle_plan_from(res["info"], case)
+    info = res["info"]
+    pl = oracle_plan_from(info, case)
     d2 = o2.degrid(case["uvw"], case["freq"], case["dirty"], pl)
     i2 = o2.grid(case["uvw"], case["freq"], case["vis"], pl)
-    # difference = polynomial kernel error (< 0.35 eps_k per value) + rounding.
-    # FP32 plans pick the lowest polynomial degree whose error is below
-    # max(eps_k / 20, 1e-7): at alpha = 12 (eps_k = 1.5e-9) that FP32 floor
-    # sets the difference (about 9e-6 measured), which the FP32 contract
-    # (epsilon >= 1e-5) still bounds.
-    if prec == "f64":
-        tol = max(pl["eps_k"], 1e-13)
-    else:
-        tol = max(pl["eps_k"], 3e-6) if alpha <= 8 else 1e-5
-    assert rel(res["vis"], d2) < tol
-    assert rel(res["img"], i2) < tol
+    tol = max(pl["eps_k"], 2.0 * info["rounding_error"], 1e-13)
+    # the polynomial kernel stays within its target (eps_k / 20, FP32 floor
+    # 1e-7), except at alpha <= 7, whose edge cells bound it near 0.3 eps_k
+    assert info["poly_error"] <= max(0.35 * pl["eps_k"], 1.2e-7 if prec == "f32" else 0.0)
+    ev, ei = rel(res["vis"], d2), rel(res["img"], i2)
+    print(f"   degrid {ev:.2e} grid {ei:.2e} tol {tol:.2e} (rounding estimate {info['rounding_error']:.2e}, "
+          f"amplification {info['amplification']:.1f}, poly {info['poly_error']:.1e})", flush=True)
+    assert ev < tol and ei < tol
+    if prec == "f32" and alpha == 12:
+        # a plan the rounding-aware planner accepts at eps = 1e-5
+        assert 3.0 * pl["eps_k"] + info["rounding_error"] <= 1e-5
     res["plan"].close()
 
 

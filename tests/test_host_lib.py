@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     from paper_2010_10122_amd import _lib
     lib = _lib.load()
     names = _header_functions()
-    assert len(names) >= 14
+    assert len(names) >= 18
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(_lib.EXPORTS)
@@ -130,3 +130,32 @@ def test_plan_create_rejects_invalid_arguments_before_device_work():
         assert lib.wg_plan_create(ctypes.byref(d), ctypes.byref(h)) == _lib.WG_EINVAL, kw
         assert not h.value
     assert lib.wg_plan_create(None, None) == _lib.WG_EINVAL
+
+
+def test_map_error_reproduces_printed_rows():
+    """Sect. 3.2 / Appendix A: the library's own map error function (eq.
+    maperror, sup over the retained band) at each printed (beta, mu)
+    reproduces the printed accuracy within 3 % (rows whose eps is above the
+    FP64 resolution of the evaluation)."""
+    worst = 0.0
+    for a, rows in K.TABLE.items():
+        for s, e, b, m in rows:
+            if e < 1e-13:
+                continue
+            got = wg.kernel_map_error(a, s, b, m)
+            worst = max(worst, abs(got / e - 1.0))
+            assert abs(got / e - 1.0) < 0.03, (a, s, e, got)
+    print(f"largest deviation from the printed eps: {worst:.2%}")
+
+
+@pytest.mark.parametrize("alpha,sigma", [(8, 1.45), (5, 1.6)])
+def test_kernel_search_pinned_by_oracle(alpha, sigma):
+    """The library's two-parameter search (Sect. 3.2) returns (beta, mu) whose
+    accuracy the oracle's independent map error confirms (within 3 %), and,
+    where the paper prints the row, no worse than the printed kernel."""
+    b, m, e = wg.kernel_search(alpha, sigma)
+    ref = K.kernel_accuracy(alpha, sigma, b, m, nx=1025)
+    assert abs(ref / e - 1.0) < 0.03, (e, ref)
+    if alpha in K.TABLE:
+        _, ep, _, _ = K.table_row(alpha, sigma)
+        assert e <= 1.03 * ep
