@@ -39,7 +39,10 @@ extern "C" {
 #define WG_ENOMEM       -2   /* an allocation failed                                  */
 #define WG_EHIP         -3   /* a HIP runtime call or kernel launch failed            */
 #define WG_EUNSUPPORTED -4   /* valid request outside what this library implements   */
+#define WG_ESCRATCH     -5   /* workspace larger than the allocation-free scratch     */
 
+/* Size of the fixed device scratch behind wg_apply_noalloc (per GPU). */
+#define WG_SCRATCH_BYTES ((size_t)128 << 20)
 
 /* ---- precision --------------------------------------------------------- */
 #define WG_F32 0   /* complex64 visibilities, float32 image (epsilon >= 1e-5)      */
@@ -140,6 +143,23 @@ int wg_degrid(const wg_plan *plan, const void *dirty, const void *wgt, void *vis
  * safe when each uses its own workspace and output. */
 int wg_grid(const wg_plan *plan, const void *vis, const void *wgt, void *dirty,
             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Allocation-free apply, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operators, kernels and results as wg_degrid (adjoint = 0:
+ * in = dirty image, out = visibilities) and wg_grid (adjoint != 0: in =
+ * visibilities, out = dirty image), with the same layouts, weights and
+ * masks, but the workspace is a fixed static device array of
+ * WG_SCRATCH_BYTES per GPU instead of a caller buffer.  The call makes no
+ * allocation of any kind; the first call on a device looks up that
+ * device's scratch address once.  The plan's device must be current.
+ * Every call on a GPU shares that GPU's scratch and leaves its contents
+ * behind (each call clears what it needs): calls that overlap in time on one
+ * GPU (different streams or host threads) race and give wrong results.
+ * Errors: WG_ESCRATCH when wg_workspace_bytes(plan) > WG_SCRATCH_BYTES;
+ * WG_EINVAL for NULL plan/in/out or another device current; WG_EHIP. */
+int wg_apply_noalloc(const wg_plan *plan, int adjoint, const void *in, const void *wgt, void *out,
+                     void *stream);
 
 /* Plan summary (host struct, filled by wg_plan_info). */
 typedef struct {

@@ -5,7 +5,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwgrid.so")
 
-WG_OK, WG_EINVAL, WG_ENOMEM, WG_EHIP, WG_EUNSUPPORTED = 0, -1, -2, -3, -4
+WG_OK, WG_EINVAL, WG_ENOMEM, WG_EHIP, WG_EUNSUPPORTED, WG_ESCRATCH = 0, -1, -2, -3, -4, -5
+WG_SCRATCH_BYTES = 128 << 20
 WG_F32, WG_F64 = 0, 1
 
 _alloc_fn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
@@ -77,7 +78,8 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTS = [
-    "wg_plan_create", "wg_plan_destroy", "wg_plan_estimate", "wg_degrid", "wg_grid", "wg_plan_info",
+    "wg_plan_create", "wg_plan_destroy", "wg_plan_estimate", "wg_degrid", "wg_grid", "wg_apply_noalloc",
+    "wg_plan_info",
     "wg_workspace_bytes", "wg_plan_bytes", "wg_plan_index", "wg_strerror", "wg_grid_size",
     "wg_kernel_params", "wg_select_kernel", "wg_kernel_poly", "wg_kernel_psi", "wg_kernel_search",
     "wg_kernel_map_error", "wg_kernel_table",
@@ -118,6 +120,8 @@ def load():
     for fn in (lib.wg_degrid, lib.wg_grid):
         fn.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         fn.restype = ctypes.c_int
+    lib.wg_apply_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.wg_apply_noalloc.restype = ctypes.c_int
     lib.wg_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.wg_plan_info.restype = ctypes.c_int
     lib.wg_workspace_bytes.argtypes = [vp]

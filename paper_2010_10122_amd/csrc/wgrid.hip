@@ -566,10 +566,16 @@ int plan_host(wg_plan *p) {
     return WG_OK;
 }
 
+void *scratch_for_device(int dev);
+
 int plan_build(wg_plan *p) {
     const wg_plan_desc &d = p->desc;
     hipStream_t st = p->stream;
     HIP_TRY(hipGetDevice(&p->device));
+    // set-up of the allocation-free entry point on this device (its scratch
+    // address, looked up once per device); a failure is reported by that
+    // entry point, not here
+    if (!scratch_for_device(p->device)) (void)hipGetLastError();
     p->precision = d.precision;
     p->do_w = d.do_wgridding ? 1 : 0;
     p->n_total = d.n_rows * d.n_chan;
@@ -906,6 +912,33 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
 
 }  // namespace
 
+// ---- fixed scratch of the allocation-free entry point -----------------------
+// One statically sized device array per GPU (its own copy on each device the
+// library runs on, held until the process ends).  Host code never uses the
+// array's name as an address: the device address of this device's copy is
+// looked up once per device with hipGetSymbolAddress and kept here.
+constexpr size_t kScratchBytes = WG_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up on the first call on
+// the device, with that device current); nullptr on failure.
+void *scratch_for_device(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -955,6 +988,20 @@ int wg_grid(const wg_plan *p, const void *vis, const void *wgt, void *dirty, voi
     hipStream_t st = (hipStream_t)stream;
     return p->precision == WG_F32 ? apply<float>(p, true, vis, wgt, dirty, workspace, workspace_bytes, st)
                                   : apply<double>(p, true, vis, wgt, dirty, workspace, workspace_bytes, st);
+}
+
+int wg_apply_noalloc(const wg_plan *p, int adjoint, const void *in, const void *wgt, void *out, void *stream) {
+    if (!p || !in || (!out && (adjoint || p->n_total > 0))) return WG_EINVAL;
+    if (p->ws_bytes > kScratchBytes) return WG_ESCRATCH;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device) return WG_EINVAL;
+    void *ws = scratch_for_device(dev);
+    if (!ws) return WG_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    const bool grid = adjoint != 0;
+    return p->precision == WG_F32 ? apply<float>(p, grid, in, wgt, out, ws, kScratchBytes, st)
+                                  : apply<double>(p, grid, in, wgt, out, ws, kScratchBytes, st);
 }
 
 int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
@@ -1103,6 +1150,7 @@ const char *wg_strerror(int code) {
             return s.c_str();
         }
         case WG_EUNSUPPORTED: return "unsupported request (no printed kernel reaches epsilon, or grid too large)";
+        case WG_ESCRATCH: return "the plan's workspace exceeds the fixed scratch of wg_apply_noalloc";
         default: return "unknown error";
     }
 }
