@@ -77,9 +77,6 @@ typedef struct {
                                     planner's table, see wg_kernel_table)               */
     int            planes_per_batch; /* 0 = automatic; w-planes processed per batch,
                                         capped at alpha and at 8 (FP32) / 4 (FP64)      */
-    int            fft_path;     /* 0 = automatic (full-length column passes); 1 = the
-                                    same; 2 = u transform split in two (four-step),
-                                    where the sizes allow it, else as 1                */
     void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
     wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
     wg_free_fn     free;
@@ -192,7 +189,6 @@ typedef struct {
                                  made on the grid                                    */
     double  poly_error;       /* largest |polynomial - phi| over the alpha cells of the
                                  piecewise kernel (Sect. 4.2), evaluated in FP64      */
-    int     fft_split;        /* rows per u-split stage S (0: full-length column passes) */
 } wg_plan_info_t;
 
 int    wg_plan_info(const wg_plan *plan, wg_plan_info_t *info);
@@ -205,6 +201,15 @@ size_t wg_plan_bytes(const wg_plan *plan);
  *   order [n_vis] uint32: linear index r*n_chan + c, ascending within a key.
  * Either pointer may be NULL.  Asynchronous on ``stream``. */
 int wg_plan_index(const wg_plan *plan, void *keys, void *order, void *stream);
+
+/* The gridder's own visibility order (derived from the index of Sect. 4.3):
+ * order2[t] (device uint32 [n_vis]) = linear index r*n_chan + c of the
+ * visibility at position t.  The order is by (tile, edge rank, first
+ * plane): within a 16x16 tile, rank 0 = footprint inside the tile, 1 =
+ * reaching the next tile along v only, 2 = along both u and v, 3 = along u
+ * only (the next tile meaning the one with the tile index plus one, cyclic);
+ * ties keep the index order.  Asynchronous on ``stream``. */
+int wg_plan_grid_order(const wg_plan *plan, void *order2, void *stream);
 
 const char *wg_strerror(int code);
 

@@ -30,7 +30,6 @@ class PlanDesc(ctypes.Structure):
         ("alpha", ctypes.c_int),
         ("sigma", ctypes.c_double),
         ("planes_per_batch", ctypes.c_int),
-        ("fft_path", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("alloc", _alloc_fn),
         ("free", _free_fn),
@@ -73,14 +72,13 @@ class PlanInfo(ctypes.Structure):
         ("rounding_error", ctypes.c_double),
         ("amplification", ctypes.c_double),
         ("poly_error", ctypes.c_double),
-        ("fft_split", ctypes.c_int),
     ]
 
 
 EXPORTS = [
     "wg_plan_create", "wg_plan_destroy", "wg_plan_estimate", "wg_degrid", "wg_grid", "wg_apply_noalloc",
     "wg_plan_info",
-    "wg_workspace_bytes", "wg_plan_bytes", "wg_plan_index", "wg_strerror", "wg_grid_size",
+    "wg_workspace_bytes", "wg_plan_bytes", "wg_plan_index", "wg_plan_grid_order", "wg_strerror", "wg_grid_size",
     "wg_kernel_params", "wg_select_kernel", "wg_kernel_poly", "wg_kernel_psi", "wg_kernel_search",
     "wg_kernel_map_error", "wg_kernel_table",
     "wg_profiler_create", "wg_profiler_destroy", "wg_profiler_attach", "wg_profiler_read",
@@ -130,6 +128,8 @@ def load():
     lib.wg_plan_bytes.restype = ctypes.c_size_t
     lib.wg_plan_index.argtypes = [vp, vp, vp, vp]
     lib.wg_plan_index.restype = ctypes.c_int
+    lib.wg_plan_grid_order.argtypes = [vp, vp, vp]
+    lib.wg_plan_grid_order.restype = ctypes.c_int
     lib.wg_strerror.argtypes = [ctypes.c_int]
     lib.wg_strerror.restype = ctypes.c_char_p
     lib.wg_grid_size.argtypes = [ctypes.c_double, ctypes.c_int]

@@ -14,8 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwgrid.so")
 SUPPORTS = list(range(4, 17))
 HEADERS = ["device_common.hpp", "fft_lds.hpp", "kernels_apply.hpp", "kernels_index.hpp", "host_math.hpp",
-           "plan_internal.hpp", "vis_launch.hpp", "kernel_table_search.inc", "fft_split.hpp",
-           "kernels_fft_split.hpp"]
+           "plan_internal.hpp", "vis_launch.hpp", "kernel_table_search.inc"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -27,7 +26,6 @@ FLAGS = [
 
 def _units():
     units = [("wgrid.o", os.path.join(CSRC, "wgrid.hip"), []),
-             ("fft_split.o", os.path.join(CSRC, "fft_split.hip"), []),
              ("host_math.o", os.path.join(CSRC, "host_math.cpp"), [])]
     for a in SUPPORTS:
         units.append((f"vis_a{a}.o", os.path.join(CSRC, "vis_launch.hip"), [f"-DWG_ALPHA={a}"]))

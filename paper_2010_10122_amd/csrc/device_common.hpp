@@ -146,6 +146,23 @@ __device__ __forceinline__ void sincos_turns_f32(double ph, float &sn, float &cs
     cs = (q & 2) ? -c1 : c1;
 }
 
+// The nine (tile, rank) runs of the gridder stream that tile (A, B) takes:
+// its own tile's four ranks, ranks 1-2 of the tile left (B - 1), ranks 2-3
+// of the tile above (A - 1), rank 2 of the diagonal one; returned as the row
+// (tile * 4 + rank) of the class tables.  Tiles wrap around the grid.
+constexpr int kGridSegs = 9;
+__device__ __forceinline__ int64_t grid_seg_bin(int sg, int A, int B, int ntu, int ntv) {
+    // segment -> (tile offset up, tile offset left, rank)
+    int du = 0, dv = 0, rank = sg;
+    if (sg >= 4 && sg < 6) { dv = 1; rank = sg - 3; }          // 1, 2
+    else if (sg >= 6 && sg < 8) { du = 1; rank = sg - 4; }     // 2, 3
+    else if (sg == 8) { du = 1; dv = 1; rank = 2; }
+    int tu = A - du, tv = B - dv;
+    if (tu < 0) tu += ntu;
+    if (tv < 0) tv += ntv;
+    return ((int64_t)tu * ntv + tv) * 4 + rank;
+}
+
 // blockIdx -> work-item remap that keeps neighbouring tiles on one XCD:
 // workgroups are dealt round-robin over the 8 XCDs, so give XCD x the
 // contiguous range [x * per, (x + 1) * per).  Returns -1 for padding blocks.

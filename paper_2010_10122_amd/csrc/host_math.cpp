@@ -428,7 +428,7 @@ double map_error(double x, int alpha, double beta, double mu, const std::vector<
     return std::sqrt(acc);
 }
 
-double map_error_sup(int alpha, double sigma, double beta, double mu) {
+double map_error_sup(int alpha, double sigma, double beta, double mu, bool refine) {
     std::vector<double> qt, qw;
     psi_nodes(alpha, beta, mu, qt, qw);
     const double xmax = 0.5 / sigma;
@@ -438,13 +438,23 @@ double map_error_sup(int alpha, double sigma, double beta, double mu) {
         xs[i] = xmax * i / nx;
         ls[i] = map_error(xs[i], alpha, beta, mu, qt, qw);
     }
-    // The minimax optimum equioscillates: refine every local maximum of the
-    // samples (golden section on its bracket), not only the largest one.
+    // The minimax optimum equioscillates, so every local maximum of the
+    // samples is refined, not only the largest one: by golden section on its
+    // bracket (refine), else by the vertex of the parabola through the peak
+    // sample and its neighbours (the search's cheaper objective).
     double top = 0.0;
     for (int i = 0; i <= nx; ++i) {
         top = std::max(top, ls[i]);
         const bool peak = (i == 0 || ls[i] >= ls[i - 1]) && (i == nx || ls[i] >= ls[i + 1]);
         if (!peak) continue;
+        if (!refine) {
+            if (i > 0 && i < nx) {
+                const double c = 2.0 * ls[i] - ls[i - 1] - ls[i + 1];
+                const double d = ls[i + 1] - ls[i - 1];
+                if (c > 0.0) top = std::max(top, ls[i] + d * d / (8.0 * c));
+            }
+            continue;
+        }
         double lo = xs[std::max(0, i - 1)], hi = xs[std::min(nx, i + 1)];
         const double g = 0.5 * (std::sqrt(5.0) - 1.0);
         double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
@@ -477,7 +487,7 @@ double nelder_mead(const std::function<double(double, double)> &f, double &b, do
         int o[3] = {0, 1, 2};
         std::sort(o, o + 3, [&](int x, int y) { return F[x] < F[y]; });
         const int lo = o[0], mid = o[1], hi = o[2];
-        if (std::fabs(F[hi] - F[lo]) < 1e-9 && std::fabs(P[hi][0] - P[lo][0]) + std::fabs(P[hi][1] - P[lo][1]) < 1e-7)
+        if (std::fabs(F[hi] - F[lo]) < 1e-7 && std::fabs(P[hi][0] - P[lo][0]) + std::fabs(P[hi][1] - P[lo][1]) < 1e-6)
             break;
         const double c0 = 0.5 * (P[lo][0] + P[mid][0]), c1 = 0.5 * (P[lo][1] + P[mid][1]);
         const double r0 = 2.0 * c0 - P[hi][0], r1 = 2.0 * c1 - P[hi][1];
@@ -513,7 +523,7 @@ double nelder_mead(const std::function<double(double, double)> &f, double &b, do
 double kernel_search(int alpha, double sigma, double *beta, double *mu) {
     auto f = [&](double b, double m) {
         if (!(b > 0.3 && b < 4.0 && m > 0.2 && m < 1.0)) return 1e300;
-        return std::log(map_error_sup(alpha, sigma, b, m));
+        return std::log(map_error_sup(alpha, sigma, b, m, false));
     };
     struct Start { double f, b, m; };
     std::vector<Start> starts;
@@ -535,7 +545,7 @@ double kernel_search(int alpha, double sigma, double *beta, double *mu) {
     }
     *beta = bb;
     *mu = bm;
-    return std::exp(bf);
+    return map_error_sup(alpha, sigma, bb, bm, true);
 }
 
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,

@@ -41,7 +41,7 @@ double rounding_error(int alpha, double sigma, int precision, int do_w, int npix
                       double py);
 double map_error(double x, int alpha, double beta, double mu, const std::vector<double> &qt,
                  const std::vector<double> &qw);
-double map_error_sup(int alpha, double sigma, double beta, double mu);
+double map_error_sup(int alpha, double sigma, double beta, double mu, bool refine = true);
 double kernel_search(int alpha, double sigma, double *beta, double *mu);
 int select_kernel(double eps, int precision, int do_w, int npix_x, int npix_y, double px,
                   double py, int64_t n_vis, double wmin, double wmax, int *alpha, double *sigma,

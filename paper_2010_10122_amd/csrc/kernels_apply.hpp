@@ -13,7 +13,7 @@ constexpr int kTileArea = kTileCells * kTileCells;
 #define WG_GRID_ITEM_CAP 2048
 #endif
 constexpr int kGridItemCap = WG_GRID_ITEM_CAP;   // visibilities per gridder work item
-constexpr int kDegridItemCap = 2048;             // visibilities per degridder work item
+constexpr int kDegridItemCap = 512;              // visibilities per degridder work item (one per thread)
 
 // Arguments shared by the gridder and the degridder.
 // Per selected visibility, in sorted order (built once per plan): the
@@ -173,11 +173,13 @@ __device__ __forceinline__ bool work_item(const int4 *__restrict__ extra, int n_
     return true;
 }
 
-// The four bins whose visibilities can reach tile (A, B) in batch J (the
-// tile's own and those of the three neighbours up/left), as one
-// concatenated list of sorted positions.
+// The visibilities that reach tile (A, B) in batch J: the nine runs of the
+// gridder stream (class order) that grid_seg_bin names (the tile's own bin,
+// and the parts of the bins up/left whose footprints reach into it), as one
+// concatenated list of stream positions.  a.tab_lo / a.tab_hi are the
+// stream's (tile, rank) tables.
 struct TileBins {
-    uint32_t s0[4], end[4];      // first sorted position, running end of the concatenation
+    uint32_t s0[kGridSegs], end[kGridSegs];   // first position, running end of the concatenation
     uint32_t total;
 };
 template <typename R>
@@ -186,27 +188,22 @@ __device__ __forceinline__ TileBins tile_bins(const VisArgs<R> &a, int J, int A,
     TileBins tb;
     tb.total = 0;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        int tu = A - 1 + (nb >> 1);
-        int tv = B - 1 + (nb & 1);
-        if (tu < 0) tu += g.ntu;
-        if (tv < 0) tv += g.ntv;
-        const int64_t bin = (int64_t)tu * g.ntv + tv;
+    for (int sg = 0; sg < kGridSegs; ++sg) {
+        const int64_t bin = grid_seg_bin(sg, A, B, g.ntu, g.ntv);
         const uint32_t s0 = a.tab_lo[bin * (a.NJ + 1) + J];
         const uint32_t s1 = a.tab_hi[bin * (a.NJ + 1) + J + 1];
-        tb.s0[nb] = s0;
+        tb.s0[sg] = s0;
         tb.total += s1 > s0 ? s1 - s0 : 0u;
-        tb.end[nb] = tb.total;
+        tb.end[sg] = tb.total;
     }
     return tb;
 }
-// sorted position of entry pos of the concatenation (a select chain, no
+// stream position of entry pos of the concatenation (a select chain, no
 // dynamic register indexing)
 __device__ __forceinline__ uint32_t tile_bins_pos(const TileBins &tb, uint32_t pos) {
     uint32_t s = tb.s0[0] + pos;
-    s = pos >= tb.end[0] ? tb.s0[1] + (pos - tb.end[0]) : s;
-    s = pos >= tb.end[1] ? tb.s0[2] + (pos - tb.end[1]) : s;
-    s = pos >= tb.end[2] ? tb.s0[3] + (pos - tb.end[2]) : s;
+#pragma unroll
+    for (int k = 0; k < kGridSegs - 1; ++k) s = pos >= tb.end[k] ? tb.s0[k + 1] + (pos - tb.end[k]) : s;
     return s;
 }
 // Tile-relative first cell of a footprint and the masks of the tile's rows

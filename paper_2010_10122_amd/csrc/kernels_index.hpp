@@ -210,9 +210,9 @@ __global__ void k_fill_tab(const unsigned long long *__restrict__ keys, int64_t 
 }
 
 // ---- work items -------------------------------------------------------------
-// In batch J the gridder of tile t takes the visibilities of the four bins
-// whose footprints reach t (t and its neighbours up/left), the degridder
-// those of bin t alone.  A list longer than `cap` is dealt as ceil(len/cap)
+// In batch J the gridder of tile t takes, from the gridder stream, the
+// visibilities of bin t and those of the bins up/left whose footprints reach
+// t (grid_seg_bin).  A list longer than `cap` is dealt as ceil(len/cap)
 // items: the first is implied by the launch (one block per tile), the others
 // are listed here.  Run twice: emit = 0 counts the extra items per batch into
 // cur_*, emit = 1 (cursors cleared, off_* = per-batch list offsets) writes
@@ -227,12 +227,10 @@ __device__ __forceinline__ uint32_t bin_len(const uint32_t *__restrict__ tab_lo,
     return s1 > s0 ? s1 - s0 : 0u;
 }
 
-__global__ void k_items(const uint32_t *__restrict__ tab_lo, const uint32_t *__restrict__ tab_hi, int ntu,
-                        int ntv, int NJ, uint32_t cap_g, uint32_t cap_d, int emit, uint32_t *__restrict__ cur_g,
-                        uint32_t *__restrict__ cur_d, uint32_t *__restrict__ cur_r,
-                        const uint32_t *__restrict__ off_g, const uint32_t *__restrict__ off_d,
-                        const uint32_t *__restrict__ off_r, int4 *__restrict__ items_g,
-                        int4 *__restrict__ items_d, int4 *__restrict__ red) {
+__global__ void k_items(const uint32_t *__restrict__ tab2_lo, const uint32_t *__restrict__ tab2_hi, int ntu,
+                        int ntv, int NJ, uint32_t cap_g, int emit, uint32_t *__restrict__ cur_g,
+                        uint32_t *__restrict__ cur_r, const uint32_t *__restrict__ off_g,
+                        const uint32_t *__restrict__ off_r, int4 *__restrict__ items_g, int4 *__restrict__ red) {
     const int64_t nt = (int64_t)ntu * ntv;
     const int64_t n = nt * NJ;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -240,40 +238,107 @@ __global__ void k_items(const uint32_t *__restrict__ tab_lo, const uint32_t *__r
         const int t = (int)(e - (int64_t)J * nt);
         const int A = t / ntv, B = t - (t / ntv) * ntv;
         uint32_t cg = 0;
-        for (int nb = 0; nb < 4; ++nb) {
-            int tu = A - 1 + (nb >> 1), tv = B - 1 + (nb & 1);
-            if (tu < 0) tu += ntu;
-            if (tv < 0) tv += ntv;
-            cg += bin_len(tab_lo, tab_hi, (int64_t)tu * ntv + tv, NJ, J);
-        }
-        const uint32_t cd = bin_len(tab_lo, tab_hi, t, NJ, J);
+        for (int sg = 0; sg < kGridSegs; ++sg) cg += bin_len(tab2_lo, tab2_hi, grid_seg_bin(sg, A, B, ntu, ntv), NJ, J);
         const uint32_t eg = cg > cap_g ? (cg - 1) / cap_g : 0u;
-        const uint32_t ed = cd > cap_d ? (cd - 1) / cap_d : 0u;
+        if (!eg) continue;
         if (!emit) {
-            if (eg) {
-                atomicAdd(&cur_g[J], eg);
-                atomicAdd(&cur_r[J], 1u);
-            }
-            if (ed) atomicAdd(&cur_d[J], ed);
+            atomicAdd(&cur_g[J], eg);
+            atomicAdd(&cur_r[J], 1u);
             continue;
         }
-        if (eg) {
-            const uint32_t b = atomicAdd(&cur_g[J], eg);
-            for (uint32_t k = 1; k <= eg; ++k) {
-                const uint32_t first = k * cap_g;
-                items_g[off_g[J] + b + k - 1] = make_int4(t, (int)first, (int)min(cap_g, cg - first), (int)(b + k - 1));
-            }
-            const uint32_t r = atomicAdd(&cur_r[J], 1u);
-            red[off_r[J] + r] = make_int4(t, (int)b, (int)eg, 0);
+        const uint32_t b = atomicAdd(&cur_g[J], eg);
+        for (uint32_t k = 1; k <= eg; ++k) {
+            const uint32_t first = k * cap_g;
+            items_g[off_g[J] + b + k - 1] = make_int4(t, (int)first, (int)min(cap_g, cg - first), (int)(b + k - 1));
         }
-        if (ed) {
-            const uint32_t s0 = tab_lo[(int64_t)t * (NJ + 1) + J];
-            const uint32_t b = atomicAdd(&cur_d[J], ed);
-            for (uint32_t k = 1; k <= ed; ++k) {
-                const uint32_t first = k * cap_d;
-                items_d[off_d[J] + b + k - 1] = make_int4(t, (int)(s0 + first), (int)min(cap_d, cd - first), 0);
-            }
+        const uint32_t r = atomicAdd(&cur_r[J], 1u);
+        red[off_r[J] + r] = make_int4(t, (int)b, (int)eg, 0);
+    }
+}
+
+// ---- gridder stream in edge-class order ------------------------------------
+// The gridder of tile (A, B) takes its own bin and, from the bins up/left of
+// it, only the visibilities whose footprints reach into it.  A visibility
+// anchored at tile-relative first cell (la, lb) reaches the next tile down
+// when la + alpha - 1 >= 16 and the next tile right when lb + alpha - 1 >= 16.
+// Rank within a tile: 0 interior, 1 right only, 2 both, 3 down only, so that
+// the ranks a neighbour needs ({1, 2} from the left, {2, 3} from above, {2}
+// diagonally) are contiguous.
+__device__ __forceinline__ int edge_rank(int2 an, int alpha) {
+    const int la = (an.x & 0xffff) & 15, lb = ((an.x >> 16) & 0xffff) & 15;
+    const bool down = la + alpha - 1 >= 16, right = lb + alpha - 1 >= 16;
+    return down ? (right ? 2 : 3) : (right ? 1 : 0);
+}
+
+// Keys of the gridder stream for the sorted positions s of the index:
+// ((tile * 4 + rank) * N_w + first plane); values s.  A stable sort of these
+// keeps the index order within each (tile, rank, plane).
+__global__ void k_class_keys(const unsigned long long *__restrict__ keys, const int2 *__restrict__ anc,
+                             int64_t n_active, int nw, int alpha, unsigned long long *__restrict__ keys2,
+                             uint32_t *__restrict__ vals2) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n_active;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[s];
+        const unsigned long long tile = k / (unsigned long long)nw;
+        const unsigned long long iw = k - tile * (unsigned long long)nw;
+        const int rank = edge_rank(anc[s], alpha);
+        keys2[s] = (tile * 4ull + (unsigned long long)rank) * (unsigned long long)nw + iw;
+        vals2[s] = (uint32_t)s;
+    }
+}
+
+// The gridder stream: coordinates and anchors in class order, and the map
+// from the caller's order to class-order positions (fold bit on top, all
+// ones for masked visibilities, filled beforehand).
+template <typename R>
+__global__ void k_class_stream(const uint32_t *__restrict__ perm2, const uint32_t *__restrict__ order,
+                               const R *__restrict__ z, const int2 *__restrict__ anc, int64_t n_active,
+                               R *__restrict__ z2, int2 *__restrict__ anc2, uint32_t *__restrict__ inv2) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_active;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = perm2[t];
+        z2[3 * t] = z[3 * (int64_t)s];
+        z2[3 * t + 1] = z[3 * (int64_t)s + 1];
+        z2[3 * t + 2] = z[3 * (int64_t)s + 2];
+        const int2 a = anc[s];
+        anc2[t] = a;
+        inv2[order[s]] = (uint32_t)t | (a.y < 0 ? 0x80000000u : 0u);
+    }
+}
+
+// ---- degridder work items -------------------------------------------------
+// The degridder takes the visibilities of one bin (index order).  A run
+// longer than `cap` is dealt as ceil(len/cap) items; the first is implied by
+// the launch (one block per tile), the others are listed as (tile, first
+// position, count, 0).  Run twice like k_items: emit = 0 counts, emit = 1
+// writes at per-batch offsets off.
+__global__ void k_items_deg(const uint32_t *__restrict__ tab_lo, const uint32_t *__restrict__ tab_hi, int ntu,
+                            int ntv, int NJ, uint32_t cap, int emit, uint32_t *__restrict__ cur,
+                            const uint32_t *__restrict__ off, int4 *__restrict__ items) {
+    const int64_t nt = (int64_t)ntu * ntv;
+    const int64_t n = nt * NJ;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int J = (int)(e / nt);
+        const int t = (int)(e - (int64_t)J * nt);
+        const uint32_t len = bin_len(tab_lo, tab_hi, t, NJ, J);
+        const uint32_t ex = len > cap ? (len - 1) / cap : 0u;
+        if (!ex) continue;
+        const uint32_t b = atomicAdd(&cur[J], ex);
+        if (!emit) continue;
+        const uint32_t s0 = tab_lo[(int64_t)t * (NJ + 1) + J];
+        for (uint32_t k = 1; k <= ex; ++k) {
+            const uint32_t first = k * cap;
+            items[off[J] + b + k - 1] = make_int4(t, (int)(s0 + first), (int)min(cap, len - first), 0);
         }
+    }
+}
+
+// order2[stream position] = caller's linear index, from the caller-order map
+__global__ void k_stream_order(const uint32_t *__restrict__ inv2, int64_t n_total, uint32_t *__restrict__ order2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = inv2[i];
+        if (e != 0xffffffffu) order2[e & 0x7fffffffu] = (uint32_t)i;
     }
 }
 

@@ -78,12 +78,6 @@ struct wg_plan {
     int64_t n_total = 0, n_active = 0;
     double wmin = 0, wmax = 0, predicted = 0;
     wg::FftDesc fft_u{}, fft_v{};
-    // u-axis FFT split in two (S rows x N1): S = 0 when the full-length
-    // column passes run instead; V image columns per thread in the fused
-    // row passes; Q columns per workgroup of the N1-point passes
-    int split_S = 0, split_V = 0, split_Q = 0;
-    wg::FftDesc fft_u1{};
-    void *tw_u1 = nullptr;             // complex R [N1]: e^{-2 pi i t / N1}
     int k_cols = 1;     // columns per workgroup in the strided passes
     int k_cols_d = 1;   // the same for the degridding column pass
     // device arrays
@@ -97,6 +91,12 @@ struct wg_plan {
     void *zc = nullptr;                // [n_active][3] R: kernel-local coordinates
     int2 *anc = nullptr;               // [n_active] anchors and fold bit
     uint32_t *inv = nullptr;           // [n_total] sorted position | fold << 31, ~0 if masked
+    // gridder stream: the same visibilities ordered by (tile, edge rank,
+    // first plane), with its (tile * 4 + rank, batch) range tables
+    uint32_t *tab2_lo = nullptr, *tab2_hi = nullptr;   // [tiles * 4][NJ+1]
+    void *zc2 = nullptr;               // [n_active][3] R
+    int2 *anc2 = nullptr;              // [n_active]
+    uint32_t *inv2 = nullptr;          // [n_total] stream position | fold << 31, ~0 if masked
     // extra work items per batch (lists longer than the item cap); offsets into
     // the device lists, [NJ + 1] each
     std::vector<uint32_t> xg_off, xd_off, xr_off;

@@ -2,6 +2,8 @@
 // (set by the build, once per support).
 #include "vis_launch.hpp"
 
+#include <algorithm>
+
 #ifndef WG_ALPHA
 #error "build with -DWG_ALPHA=<support>"
 #endif

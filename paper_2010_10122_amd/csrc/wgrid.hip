@@ -15,7 +15,6 @@
 #include "../../include/wgrid.h"
 #include "host_math.hpp"
 #include "kernels_apply.hpp"
-#include "fft_split.hpp"
 #include "kernels_index.hpp"
 #include "plan_internal.hpp"
 #include "vis_launch.hpp"
@@ -176,8 +175,7 @@ namespace {
 
 template <typename R> int build_plan_tables(wg_plan *p, const std::vector<double> &coefd,
                                             const std::vector<double> &twu_re, const std::vector<double> &twu_im,
-                                            const std::vector<double> &twv_re, const std::vector<double> &twv_im,
-                                            const std::vector<double> &tw1_re, const std::vector<double> &tw1_im) {
+                                            const std::vector<double> &twv_re, const std::vector<double> &twv_im) {
     using C = Cx<R>;
     std::vector<R> cr(coefd.size());
     for (size_t i = 0; i < coefd.size(); ++i) cr[i] = (R)coefd[i];
@@ -193,13 +191,6 @@ template <typename R> int build_plan_tables(wg_plan *p, const std::vector<double
     if (!p->tw_u || !p->tw_v) return WG_ENOMEM;
     HIP_TRY(hipMemcpyAsync(p->tw_u, tu.data(), tu.size() * sizeof(C), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->tw_v, tv.data(), tv.size() * sizeof(C), hipMemcpyHostToDevice, st));
-    std::vector<C> t1(tw1_re.size());
-    if (!t1.empty()) {
-        for (size_t i = 0; i < t1.size(); ++i) { t1[i].x = (R)tw1_re[i]; t1[i].y = (R)tw1_im[i]; }
-        p->tw_u1 = p->mem.get(t1.size() * sizeof(C));
-        if (!p->tw_u1) return WG_ENOMEM;
-        HIP_TRY(hipMemcpyAsync(p->tw_u1, t1.data(), t1.size() * sizeof(C), hipMemcpyHostToDevice, st));
-    }
     HIP_TRY(hipStreamSynchronize(st));   // the host vectors must outlive the copies
     return WG_OK;
 }
@@ -271,8 +262,57 @@ int radix_sort(wg_plan *p, unsigned long long *const keys_io, uint32_t *const va
     return rc;
 }
 
-// Extra work items of every batch (see k_items): count, lay out per batch,
-// emit.  Leaves xg/xd/xr and their per-batch offsets in the plan.
+// Gridder stream (see k_class_keys): keys (tile * 4 + edge rank) * N_w +
+// first plane of the sorted positions, stably sorted; range tables per
+// (tile, rank, batch); coordinates, anchors and the caller-order map in the
+// new order.  Needs the index (keys, order, tables), zc and anc.
+int build_class_stream(wg_plan *p, hipStream_t st, int bits) {
+    const Geom &g = p->g;
+    const int64_t nact = std::max<int64_t>(p->n_active, 1);
+    const size_t sr = p->precision == WG_F32 ? 4 : 8;
+    const unsigned long long tab2_n = (unsigned long long)g.ntu * g.ntv * 4ull * (unsigned long long)(p->NJ + 1);
+    p->tab2_lo = (uint32_t *)p->mem.get(tab2_n * sizeof(uint32_t));
+    p->tab2_hi = (uint32_t *)p->mem.get(tab2_n * sizeof(uint32_t));
+    p->zc2 = p->mem.get(nact * 3 * sr);
+    p->anc2 = (int2 *)p->mem.get(nact * sizeof(int2));
+    p->inv2 = (uint32_t *)p->mem.get(std::max<int64_t>(p->n_total, 1) * sizeof(uint32_t));
+    unsigned long long *keys2 = (unsigned long long *)p->mem.get(nact * sizeof(unsigned long long));
+    uint32_t *perm2 = (uint32_t *)p->mem.get(nact * sizeof(uint32_t));
+    if (!p->tab2_lo || !p->tab2_hi || !p->zc2 || !p->anc2 || !p->inv2 || !keys2 || !perm2) return WG_ENOMEM;
+    const unsigned grid = (unsigned)grid_blocks(p->n_active, 256, 1 << 20);
+    if (p->n_total > 0)
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 20)), dim3(256), 0, st,
+                           p->inv2, p->n_total, 0xffffffffu);
+    int rc = WG_OK;
+    if (p->n_active > 0) {
+        hipLaunchKernelGGL(k_class_keys, dim3(grid), dim3(256), 0, st, p->keys, p->anc, p->n_active, g.nw, g.alpha,
+                           keys2, perm2);
+        LAUNCH_CHECK("k_class_keys");
+        rc = radix_sort(p, keys2, perm2, p->n_active, bits + 2, st);
+        if (rc != WG_OK) return rc;
+        if (p->precision == WG_F32)
+            hipLaunchKernelGGL(k_class_stream<float>, dim3(grid), dim3(256), 0, st, perm2, p->order,
+                               (const float *)p->zc, p->anc, p->n_active, (float *)p->zc2, p->anc2, p->inv2);
+        else
+            hipLaunchKernelGGL(k_class_stream<double>, dim3(grid), dim3(256), 0, st, perm2, p->order,
+                               (const double *)p->zc, p->anc, p->n_active, (double *)p->zc2, p->anc2, p->inv2);
+        LAUNCH_CHECK("k_class_stream");
+    }
+    hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
+                       keys2, p->n_active, g.nw, p->P, p->NJ, p->alpha - 1, tab2_n, p->tab2_lo);
+    hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
+                       keys2, p->n_active, g.nw, p->P, p->NJ, 0, tab2_n, p->tab2_hi);
+    LAUNCH_CHECK("k_fill_tab (class)");
+    HIP_TRY(hipStreamSynchronize(st));
+    p->mem.put(keys2);
+    p->mem.put(perm2);
+    return rc;
+}
+
+// Extra work items of every batch (gridder: k_items over the gridder
+// stream; degridder: k_items_deg over the index): count, lay out per batch,
+// emit.  Leaves
+// xg/xd/xr and their per-batch offsets in the plan.
 int build_items(wg_plan *p, hipStream_t st) {
     const int NJ = p->NJ;
     const int64_t n = (int64_t)p->g.ntu * p->g.ntv * NJ;
@@ -283,9 +323,11 @@ int build_items(wg_plan *p, hipStream_t st) {
     const unsigned nb = (unsigned)grid_blocks(n, 256, 1 << 16);
     hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3((unsigned)grid_blocks(6 * NJ, 256, 1024)), dim3(256), 0, st, cur,
                        (int64_t)6 * NJ);
-    hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
-                       (uint32_t)kGridItemCap, (uint32_t)kDegridItemCap, 0, cur_g, cur_d, cur_r, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab2_lo, p->tab2_hi, p->g.ntu, p->g.ntv, NJ,
+                       (uint32_t)kGridItemCap, 0, cur_g, cur_r, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_items_deg, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
+                       (uint32_t)kDegridItemCap, 0, cur_d, nullptr, nullptr);
+    LAUNCH_CHECK("k_items");
     std::vector<uint32_t> cnt((size_t)3 * NJ);
     HIP_TRY(hipMemcpyAsync(cnt.data(), cur, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -314,9 +356,10 @@ int build_items(wg_plan *p, hipStream_t st) {
         HIP_TRY(hipMemcpyAsync(doff, offs.data(), offs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3((unsigned)grid_blocks(3 * NJ, 256, 1024)), dim3(256), 0, st,
                            cur, (int64_t)3 * NJ);
-        hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
-                           (uint32_t)kGridItemCap, (uint32_t)kDegridItemCap, 1, cur_g, cur_d, cur_r, doff,
-                           doff + NJ, doff + 2 * NJ, p->xg, p->xd, p->xr);
+        hipLaunchKernelGGL(k_items, dim3(nb), dim3(256), 0, st, p->tab2_lo, p->tab2_hi, p->g.ntu, p->g.ntv, NJ,
+                           (uint32_t)kGridItemCap, 1, cur_g, cur_r, doff, doff + 2 * NJ, p->xg, p->xr);
+        hipLaunchKernelGGL(k_items_deg, dim3(nb), dim3(256), 0, st, p->tab_lo, p->tab_hi, p->g.ntu, p->g.ntv, NJ,
+                           (uint32_t)kDegridItemCap, 1, cur_d, doff + NJ, p->xd);
         if (!hip_ok(hipGetLastError(), "k_items")) return WG_EHIP;
         HIP_TRY(hipStreamSynchronize(st));   // the host offsets buffer must outlive the copy
     }
@@ -342,7 +385,6 @@ int validate(const wg_plan_desc *d) {
         if (!find_row(d->alpha, d->sigma)) return WG_EINVAL;
     }
     if (d->planes_per_batch < 0) return WG_EINVAL;
-    if (d->fft_path < 0 || d->fft_path > 2) return WG_EINVAL;
     double l = (double)(0 - d->npix_x / 2) * d->pixsize_x;
     double m = (double)(0 - d->npix_y / 2) * d->pixsize_y;
     if (!(l * l + m * m < 1.0)) return WG_EINVAL;
@@ -389,12 +431,13 @@ void plan_footprint(const wg_plan *p, size_t &resident, size_t &peak) {
     const uint64_t span = (uint64_t)((p->alpha - 1 + p->P - 1) / p->P + 1);   // batches a visibility meets
     const uint64_t items = 3 * (4 * nact * span / (uint64_t)kDegridItemCap + (uint64_t)p->NJ) + 3;
     resident = (size_t)(p->desc.n_chan * 8 + (uint64_t)(p->alpha + 4) * p->alpha * sr +
-                        (uint64_t)(g.nu + g.nv) * sc + 2 * npix * 8 + ntot * (8 + 4 + 4) + 2 * tab_n * 4 +
-                        nact * (3 * sr + 8) + items * 16);
+                        (uint64_t)(g.nu + g.nv) * sc +
+                        2 * npix * 8 + ntot * (8 + 4 + 4 + 4) + 2 * tab_n * 4 * 5 + 2 * nact * (3 * sr + 8) +
+                        items * 16);
     // construction also holds the radix-sort scratch (second key and value
     // buffers, histograms, scan levels) and small host-table copies
     const uint64_t nblocks = (ntot + kRsTile - 1) / kRsTile;
-    const uint64_t sort = ntot * 12 + 256 * nblocks * 4 * 2 + 4096;
+    const uint64_t sort = ntot * 12 + 256 * nblocks * 4 * 2 + 4096 + nact * 24;   // index sort; class keys + sort
     const uint64_t tables = (uint64_t)(g.npix_x + g.npix_y) * 8 + 2 * 1024 * 8 + (uint64_t)6 * p->NJ * 4;
     peak = resident + (size_t)(sort + tables);
 }
@@ -446,43 +489,6 @@ int plan_scale(const wg_plan_desc &d, DevMem &mem, hipStream_t st, double *&scal
     HIP_TRY(hipMemcpyAsync(scale_dev, scale.data(), d.n_chan * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));   // the host vector must outlive the copy
     return WG_OK;
-}
-
-// Form of the u-axis FFT passes.  The split (four-step) form needs: the
-// fused row passes' register share of S rows (S * V values a thread, V =
-// image columns per thread of a 1024-thread workgroup: at most 32 complex
-// values in FP32, 16 in FP64), N1 = N_u / S of at least two FFT passes, and
-// a column block Q >= 8 whose N1-point transforms fit 48 KB of LDS with the
-// batch sums.  Otherwise the full-length column passes run.
-void plan_split(wg_plan *p) {
-    const Geom &g = p->g;
-    p->split_S = p->split_V = p->split_Q = 0;
-    if (p->desc.fft_path != 2) return;
-    const size_t sc = p->precision == WG_F32 ? 8 : 16;
-    const int V = (g.npix_y + kSplitThreads - 1) / kSplitThreads;
-    const int cap = p->precision == WG_F32 ? 32 : 16;
-    int S = 0;
-    for (int s : {16, 8, 4})
-        if (s * (V <= 1 ? 1 : V <= 2 ? 2 : 4) <= cap && V <= 4) {
-            S = s;
-            break;
-        }
-    if (!S || g.nu % S || g.nv > kSplitThreads * 12) return;
-    const int N1 = g.nu / S;
-    FftDesc f1;
-    make_fft_desc(N1, f1);
-    if (f1.npass < 2) return;
-    int Q = 0;
-    for (int q = 64; q >= 8; q /= 2)
-        if ((size_t)fft_lds_len(N1) * q * sc + (size_t)N1 * q * (sc / 2) <= 48 * 1024 && N1 * q <= 256 * kFftMaxC) {
-            Q = q;
-            break;
-        }
-    if (!Q) return;
-    p->split_S = S;
-    p->split_V = V <= 1 ? 1 : V <= 2 ? 2 : 4;
-    p->split_Q = Q;
-    p->fft_u1 = f1;
 }
 
 // Host planning once the w range and the active count are known: kernel
@@ -562,7 +568,6 @@ int plan_host(wg_plan *p) {
     p->NJ = (g.nw + p->P - 1) / p->P;
     make_fft_desc(g.nu, p->fft_u);
     make_fft_desc(g.nv, p->fft_v);
-    plan_split(p);
     return WG_OK;
 }
 
@@ -601,12 +606,11 @@ int plan_build(wg_plan *p) {
     std::vector<double> psix(d.npix_x), psiy(d.npix_y);
     for (int i = 0; i < d.npix_x; ++i) psix[i] = psi_eval((double)(i - d.npix_x / 2) / g.nu, qt, qw);
     for (int i = 0; i < d.npix_y; ++i) psiy[i] = psi_eval((double)(i - d.npix_y / 2) / g.nv, qt, qw);
-    std::vector<double> tur, tui, tvr, tvi, t1r, t1i;
+    std::vector<double> tur, tui, tvr, tvi;
     twiddles(g.nu, tur, tui);
     twiddles(g.nv, tvr, tvi);
-    if (p->split_S) twiddles(g.nu / p->split_S, t1r, t1i);
-    rc = d.precision == WG_F32 ? build_plan_tables<float>(p, coefd, tur, tui, tvr, tvi, t1r, t1i)
-                               : build_plan_tables<double>(p, coefd, tur, tui, tvr, tvi, t1r, t1i);
+    rc = d.precision == WG_F32 ? build_plan_tables<float>(p, coefd, tur, tui, tvr, tvi)
+                               : build_plan_tables<double>(p, coefd, tur, tui, tvr, tvi);
     if (rc != WG_OK) return rc;
 
     // correction factors
@@ -653,11 +657,6 @@ int plan_build(wg_plan *p) {
     hipLaunchKernelGGL(k_fill_tab, dim3((unsigned)grid_blocks(p->n_active + 1, 256, 1 << 20)), dim3(256), 0, st,
                        p->keys, p->n_active, g.nw, p->P, p->NJ, 0, tab_n, p->tab_hi);
     LAUNCH_CHECK("k_fill_tab");
-    // work items: lists of the gridder and degridder beyond the item cap
-    {
-        rc = build_items(p, st);
-        if (rc != WG_OK) return rc;
-    }
     // sorted per-visibility stream: kernel-local coordinates and anchors
     const int64_t nact = std::max<int64_t>(p->n_active, 1);
     p->zc = p->mem.get(nact * 3 * sr);
@@ -683,8 +682,14 @@ int plan_build(wg_plan *p) {
                                st, p->order, p->anc, p->n_active, p->inv);
         LAUNCH_CHECK("k_inv_order");
     }
-    p->index_bytes += nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 2 * tab_n * sizeof(uint32_t) +
-                      nact * (3 * sr + sizeof(int2)) + std::max<int64_t>(p->n_total, 1) * sizeof(uint32_t);
+    // gridder stream: the index re-sorted by (tile, edge rank, first plane)
+    rc = build_class_stream(p, st, bits);
+    if (rc != WG_OK) return rc;
+    // work items: lists of the gridder and degridder beyond the item cap
+    rc = build_items(p, st);
+    if (rc != WG_OK) return rc;
+    p->index_bytes += nkeys * (sizeof(unsigned long long) + sizeof(uint32_t)) + 6 * tab_n * sizeof(uint32_t) +
+                      2 * nact * (3 * sr + sizeof(int2)) + 2 * std::max<int64_t>(p->n_total, 1) * sizeof(uint32_t);
     HIP_TRY(hipStreamSynchronize(st));
     p->mem.put(dpx);
     p->mem.put(dpy);
@@ -797,10 +802,11 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     C *part = (C *)(w + p->off_part);
     const int64_t npix = (int64_t)g.npix_x * g.npix_y;
 
+    // degridder: the index order; gridder: the class-ordered stream
     VisArgs<R> va;
     va.z = (const R *)p->zc;
     va.anc = p->anc;
-    va.vsorted = vacc;              // gridding: the sorted input lives where degridding accumulates
+    va.vsorted = nullptr;
     va.tab_lo = p->tab_lo;
     va.tab_hi = p->tab_hi;
     va.coef = (const R *)p->coef;
@@ -808,6 +814,12 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     va.P = p->P;
     va.NJ = p->NJ;
     va.g = g;
+    VisArgs<R> vg = va;
+    vg.z = (const R *)p->zc2;
+    vg.anc = p->anc2;
+    vg.vsorted = vacc;              // gridding: the ordered input lives where degridding accumulates
+    vg.tab_lo = p->tab2_lo;
+    vg.tab_hi = p->tab2_hi;
     PassGeom pg{g.nu, g.nv, g.npix_x, g.npix_y, p->P, g.nw, g.do_w, g.w0, g.dw};
 
     if (gridding) {
@@ -820,35 +832,23 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
             {
                 ProfScope ps(WG_KIND_VIS, st);
                 hipLaunchKernelGGL(k_gather_vis<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256),
-                                   0, st, (const C *)in, (const R *)wgt, p->inv, p->n_total, vacc);
+                                   0, st, (const C *)in, (const R *)wgt, p->inv2, p->n_total, vacc);
             }
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
                 {
                     ProfScope ps(WG_KIND_GRID, st);
-                    launch_vis_kernel<R>(true, p, va, J, G, nullptr, part, st);
+                    launch_vis_kernel<R>(true, p, vg, J, G, nullptr, part, st);
                 }
-                if (p->split_S) {
-                    {
-                        ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
-                        split_rows_grid<R>(p, G, T, np, st);
-                    }
-                    {
-                        ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
-                        split_cols_grid<R>(p, T, acc, j_lo, np, st);
-                    }
-                } else {
-                    {
-                        ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
-                        DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
-                    }
-                    {
-                        ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
-                        DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
-                    }
+                                {
+                    ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
                 }
-            }
+                {
+                    ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
+                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                }            }
         }
         {
             ProfScope ps(WG_KIND_IMAGE, st);
@@ -875,26 +875,14 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
-                if (p->split_S) {
-                    {
-                        ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
-                        split_cols_degrid<R>(p, itil, T, j_lo, np, st);
-                    }
-                    {
-                        ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
-                        split_rows_degrid<R>(p, T, G, np, st);
-                    }
-                } else {
-                    {
-                        ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
-                        DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
-                    }
-                    {
-                        ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
-                        DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
-                    }
+                                {
+                    ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
+                    DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
                 }
                 {
+                    ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
+                    DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
+                }                {
                     ProfScope ps(WG_KIND_DEGRID, st);
                     launch_vis_kernel<R>(false, p, va, J, G, vacc, nullptr, st);
                 }
@@ -1046,7 +1034,6 @@ int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
     info->rounding_error = p->round_err;
     info->amplification = p->amp;
     info->poly_error = p->poly_err;
-    info->fft_split = p->split_S;
     return WG_OK;
 }
 
@@ -1092,6 +1079,15 @@ int wg_plan_index(const wg_plan *p, void *keys, void *order, void *stream) {
         HIP_TRY(hipMemcpyAsync(keys, p->keys, p->n_active * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
     if (order)
         HIP_TRY(hipMemcpyAsync(order, p->order, p->n_active * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    return WG_OK;
+}
+
+int wg_plan_grid_order(const wg_plan *p, void *order2, void *stream) {
+    if (!p || (!order2 && p->n_active > 0)) return WG_EINVAL;
+    if (p->n_active == 0) return WG_OK;
+    hipLaunchKernelGGL(k_stream_order, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 20)), dim3(256), 0,
+                       (hipStream_t)stream, p->inv2, p->n_total, (uint32_t *)order2);
+    LAUNCH_CHECK("k_stream_order");
     return WG_OK;
 }
 

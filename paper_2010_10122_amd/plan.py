@@ -63,7 +63,7 @@ class _TorchAllocator:
 
 
 def _fill_desc(d, uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision, do_wgridding,
-               alpha, sigma, planes_per_batch, stream, allocator, fft_path=0):
+               alpha, sigma, planes_per_batch, stream, allocator):
     d.uvw = uvw.data_ptr()
     d.freq = freq.data_ptr()
     d.mask = mask.data_ptr() if mask is not None else None
@@ -79,7 +79,6 @@ def _fill_desc(d, uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon
     d.alpha = int(alpha or 0)
     d.sigma = float(sigma or 0.0)
     d.planes_per_batch = int(planes_per_batch or 0)
-    d.fft_path = {None: 0, 0: 0, "auto": 0, 1: 1, "columns": 1, 2: 2, "split": 2}[fft_path]
     d.stream = _stream_handle(stream).value
     if allocator is not None:
         d.alloc = allocator.c_alloc
@@ -95,13 +94,12 @@ class Plan:
     alive by the plan and must not be modified while it is in use.
     precision: "f32" (epsilon >= 1e-5) or "f64".
     alpha/sigma force a kernel of the planner's table (wg_kernel_table);
-    planes_per_batch forces the w-plane batch size; fft_path "columns" or
-    "split" forces the form of the u-axis FFT passes.
+    planes_per_batch forces the w-plane batch size.
     """
 
     def __init__(self, uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision="f32",
                  do_wgridding=True, mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None,
-                 torch_allocator=True, fft_path=None):
+                 torch_allocator=True):
         lib = _lib.load()
         for name, t, dt in (("uvw", uvw, torch.float64), ("freq", freq, torch.float64)):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
@@ -124,8 +122,7 @@ class Plan:
         # (torch_allocator=False: hipMalloc / hipFree inside the library)
         self._alloc = _TorchAllocator(self.device, stream) if torch_allocator else None
         d = _fill_desc(_lib.PlanDesc(), uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon,
-                       self.precision, do_wgridding, alpha, sigma, planes_per_batch, stream, self._alloc,
-                       fft_path)
+                       self.precision, do_wgridding, alpha, sigma, planes_per_batch, stream, self._alloc)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             rc = lib.wg_plan_create(ctypes.byref(d), ctypes.byref(handle))
@@ -230,6 +227,16 @@ class Plan:
         _lib.check(self._lib.wg_plan_index(self._h, _dev_ptr(keys), _dev_ptr(order), _stream_handle(stream)),
                    "wg_plan_index")
         return keys, order
+
+
+    def grid_order(self, stream=None):
+        """Linear indices of the visibilities in the gridder's own order
+        (by tile, edge rank and first plane; ``wg_plan_grid_order``)."""
+        n = int(self.info["n_vis"])
+        order2 = torch.empty(n, dtype=torch.int32, device=self.device)
+        _lib.check(self._lib.wg_plan_grid_order(self._h, _dev_ptr(order2), _stream_handle(stream)),
+                   "wg_plan_grid_order")
+        return order2
 
 
 class Profiler:

@@ -103,3 +103,34 @@ def check_binning_full(case, plan, torch, mask=None, chunk_rows=1 << 20):
         checked += len(b["key"])
     assert checked == n
     return checked
+
+
+def check_grid_order(case, plan, torch, mask=None):
+    """The gridder's own order (by tile, edge rank, first plane) against the
+    oracle's binning spec: a permutation of the selected visibilities, whose
+    (tile * 4 + rank, first plane) sequence is sorted with ties in index
+    order, where each visibility's rank is the one its footprint implies
+    (reaches the next tile along v: 1, along u: 3, both: 2, neither: 0)."""
+    import numpy as np
+    from oracle import plan as P
+    info = plan.info
+    pl = oracle_plan_from(info, case, mask)
+    b = P.bin_visibilities(case["uvw"], case["freq"], pl, mask)
+    alpha = info["alpha"]
+    down = (b["iu"] % 16) + alpha - 1 >= 16
+    right = (b["iv"] % 16) + alpha - 1 >= 16
+    rank = np.where(down, np.where(right, 2, 3), np.where(right, 1, 0))
+    tile = (b["iu"] // 16) * (pl["nv"] // 16) + (b["iv"] // 16)
+    key2 = (tile * 4 + rank) * pl["nw"] + b["iw"]
+    pos_of = np.full(case["uvw"].shape[0] * len(case["freq"]), -1, dtype=np.int64)
+    pos_of[b["idx"]] = np.arange(len(b["idx"]))
+    order2 = plan.grid_order().cpu().numpy().astype(np.int64)
+    assert len(order2) == len(b["idx"])
+    assert np.array_equal(np.sort(order2), np.sort(b["idx"]))      # a permutation of the selected ones
+    k = key2[pos_of[order2]]
+    assert np.all(k[1:] >= k[:-1])
+    tie = k[1:] == k[:-1]
+    spec_pos = np.argsort(np.argsort(b["key"], kind="stable"), kind="stable")   # position in the index
+    sp = spec_pos[pos_of[order2]]
+    assert np.all(sp[1:][tie] > sp[:-1][tie])
+    return int(np.bincount(rank, minlength=4).sum())

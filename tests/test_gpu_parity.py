@@ -310,3 +310,20 @@ def test_invalid_arguments(dev):
             wg.Plan(uvw, freq, kw.get("npix_x", 64), 64, pix, pix, kw.get("eps", 1e-5), kw.get("prec", "f32"))
     with pytest.raises(wg.WgridError):
         wg.Plan(uvw, freq, 64, 64, case["pixsize_x"], case["pixsize_y"], 1e-5, "f32", alpha=12, sigma=1.85)
+
+
+@pytest.mark.parametrize("which", ["small", "multichan", "masked"])
+def test_grid_stream_order(dev, which):
+    """The gridder's stream (edge classes within each tile) against the
+    oracle's anchors: each visibility once, in the class its footprint
+    implies, sorted by (tile, class, first plane)."""
+    from gpu_util import check_grid_order
+    case = _case_small() if which == "small" else _case_multichan()
+    mask = None
+    if which == "masked":
+        mask = (np.random.default_rng(3).random(case["vis"].shape) > 0.3).astype(np.uint8)
+    for prec, eps in (("f64", 1e-10), ("f32", 1e-5)):
+        res = run_product(case, eps, prec, torch, dev, mask=mask)
+        n = check_grid_order(case, res["plan"], torch, mask)
+        print(f"[grid order] {which} {prec}: {n} visibilities", flush=True)
+        res["plan"].close()
