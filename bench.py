@@ -11,6 +11,14 @@ resident on the device; plan construction is timed separately (cold).
 value = visibilities / mean time of one operator application, FP32 at
 epsilon = 1e-5; the plain FP64 form at the same epsilon is timed beside it.
 
+Further legs after the headline (each can be switched off; --quick runs the
+headline alone): FP64 at eps 1e-5 and 1e-10, differentiation, a serving
+load sweep, run time against epsilon (Sect. 6.3), the Sect. 6 benchmark
+shape (Sect. 6.1 FP32 eps 1e-4; Sect. 6.2 FP64 eps 1e-10 without w, multi-
+channel and flattened), the large workload, and last the CPU leg: the
+oracle timed on a bounded slice (cpu_baseline) and the sampled accuracy of
+every leg's outputs against the oracle's direct sum.
+
 Prints one JSON line.  --gpus N with N > 1 is refused: the operator runs on
 one GPU (sharding over GPUs is not implemented).
 """
@@ -177,54 +185,289 @@ def cpu_baseline(case, info, n_vis, sample_rows=800_000, seed=99):
     }
 
 
-def serving(case, count, dev, load=0.8, seed=4):
-    """Serving workload: a mix of degrid/grid requests (image sizes 512^2 to
-    4096^2, 1e5 to 2e7 visibilities drawn from the wide-field array, epsilon
-    1e-4 to 1e-9, FP32 for eps >= 1e-5 else FP64).  First all requests at
-    once (closed loop, plans built on demand) to find the saturated rate, then
-    the same requests as a Poisson stream at ``load`` times that rate with the
-    plans resident; p50/p99 latency and Mvis/s of both."""
+def serving(case, count, dev, checks, loads=(0.5, 0.8, 0.95), seed=4, n_configs=12):
+    """Serving workload: ``count`` degrid/grid requests over ``n_configs``
+    operator configurations (image sizes 512^2 to 4096^2, 1e5 to 2e7
+    visibilities drawn from the wide-field array, epsilon 1e-4 to 1e-9, FP32
+    for eps >= 1e-5 else FP64), each request with its own seeded data.
+
+    * closed loop with plans built on demand (cold), then again with the
+      plans resident (warm): the saturated request rate;
+    * Poisson arrivals at each offered load rho times the saturated rate,
+      with p50/p99 latency; every output there must equal the warm output of
+      the same request bit for bit (the apply path is deterministic);
+    * every warm output is checked against the direct sum on 4 sampled
+      entries in the accuracy leg at the end (``checks``)."""
     import numpy as np
     import torch
 
     import synth
     from paper_2010_10122_amd.serve import Request, Server, summarize
 
-    _, specs = synth.serving_requests(seed=seed, count=count, base=case)
+    _, configs, specs = synth.serving_requests(seed=seed, count=count, n_configs=n_configs, base=case)
     coords = {}
+    for c in configs:
+        r0, r1 = c["rows"]
+        key = (r0, r1, c["nchan"])
+        if key not in coords:
+            coords[key] = (torch.from_numpy(np.ascontiguousarray(case["uvw"][r0:r1])).to(dev),
+                           torch.from_numpy(np.ascontiguousarray(case["freq"][:c["nchan"]])).to(dev))
     reqs = []
     for sp in specs:
         r0, r1 = sp["rows"]
         key = (r0, r1, sp["nchan"])
-        if key not in coords:
-            coords[key] = (torch.from_numpy(np.ascontiguousarray(case["uvw"][r0:r1])).to(dev),
-                           torch.from_numpy(np.ascontiguousarray(case["freq"][:sp["nchan"]])).to(dev))
         uvw, freq = coords[key]
-        rng = np.random.default_rng(sp["seed"])
+        g = torch.Generator(device=dev).manual_seed(sp["seed"])
         if sp["direction"] == "degrid":
-            data = torch.from_numpy(rng.standard_normal((sp["npix"], sp["npix"]))).to(
-                dev, torch.float32 if sp["precision"] == "f32" else torch.float64)
+            data = torch.randn((sp["npix"], sp["npix"]), generator=g, device=dev,
+                               dtype=torch.float32 if sp["precision"] == "f32" else torch.float64)
         else:
-            data = torch.from_numpy(synth.complex_gaussian(rng, (r1 - r0, sp["nchan"]))).to(
-                dev, torch.complex64 if sp["precision"] == "f32" else torch.complex128)
+            data = torch.randn((r1 - r0, sp["nchan"]), generator=g, device=dev,
+                               dtype=torch.complex64 if sp["precision"] == "f32" else torch.complex128)
         reqs.append(Request(sp["rid"], sp["direction"], key, uvw, freq, sp["npix"], sp["pixsize"],
                             sp["epsilon"], sp["precision"], data))
+    torch.cuda.synchronize()
+
+    def digest(res):
+        # exact fingerprint of each output: its words summed as int64
+        out = {}
+        for r in res:
+            o = r.output.reshape(-1)
+            o = torch.view_as_real(o) if o.is_complex() else o
+            w = o.contiguous().view(torch.int64 if o.element_size() == 8 else torch.int32)
+            out[r.rid] = int(w.to(torch.int64).sum())
+        return out
+
     srv = Server(dev, n_slots=4)
     res, makespan = srv.run(reqs, realtime=False)
-    closed = summarize(res, makespan)
-    print(f"[bench] serving closed loop: {closed}", file=sys.stderr, flush=True)
-    rate = len(reqs) / makespan * load
-    arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate, len(reqs)))
-    for r, t in zip(reqs, arr):
-        r.arrival = float(t)
-    res, makespan = srv.run(reqs, realtime=True)
-    poisson = summarize(res, makespan)
-    poisson["offered_rate_per_s"] = rate
-    print(f"[bench] serving Poisson: {poisson}", file=sys.stderr, flush=True)
+    cold = summarize(res, makespan)
+    print(f"[bench] serving closed loop, plans built on demand: {cold}", file=sys.stderr, flush=True)
+    del res
+    res, makespan = srv.run(reqs, realtime=False)
+    warm = summarize(res, makespan)
+    print(f"[bench] serving closed loop, plans resident: {warm}", file=sys.stderr, flush=True)
+    ref_digest = digest(res)
+    warm_out = {r.rid: r.output for r in res}
+    del res
+    rate = len(reqs) / makespan
+    points = []
+    mismatches = 0
+    for k, rho in enumerate(loads):
+        arr = np.cumsum(np.random.default_rng(seed + 1 + k).exponential(1.0 / (rho * rate), len(reqs)))
+        for r, t in zip(reqs, arr):
+            r.arrival = float(t)
+        res, makespan = srv.run(reqs, realtime=True)
+        s = summarize(res, makespan)
+        s["offered_load"] = rho
+        s["offered_rate_per_s"] = rho * rate
+        d = digest(res)
+        s["outputs_equal_to_warm"] = sum(d[rid] == ref_digest[rid] for rid in d)
+        mismatches += len(d) - s["outputs_equal_to_warm"]
+        points.append(s)
+        print(f"[bench] serving Poisson rho={rho}: {s}", file=sys.stderr, flush=True)
+        del res
+    stats = {str(k): v for k, v in srv.stats.items()}
     srv.close()
-    return {"requests": len(reqs), "slots": 4, "closed_loop": closed, "poisson": poisson,
-            "mix": "image 512^2-4096^2, 1e5-2e7 vis (log-uniform), eps 1e-4/1e-5 FP32, 1e-7/1e-9 FP64, "
-                   "degrid/grid 50/50"}
+    out = {"requests": len(reqs), "configs": len(configs), "slots": 4, "closed_loop_cold": cold,
+           "closed_loop_warm": warm, "saturated_rate_per_s": rate, "poisson": points,
+           "bitwise_mismatches_vs_warm": mismatches, "server_stats": stats,
+           "mix": (f"{len(configs)} configurations: image 512^2-4096^2, 1e5-2e7 vis (log-uniform), eps "
+                   "1e-4/1e-5 FP32, 1e-7/1e-9 FP64; requests uniform over them, degrid/grid 50/50")}
+
+    def check():
+        import numpy as np
+
+        from oracle import o1
+        rng = np.random.default_rng(9)
+        worst = 0.0
+        for req in reqs:
+            r0, r1, nch = req.coord_key
+            o = warm_out[req.rid]
+            if req.direction == "degrid":
+                idx = rng.choice(req.n_vis, size=4, replace=False)
+                got = o.reshape(-1)[torch.from_numpy(idx).to(o.device)].cpu().numpy()
+                ref = o1.forward(case["uvw"][r0:r1], case["freq"][:nch], req.data.cpu().numpy(), req.pixsize,
+                                 req.pixsize, vis_idx=idx)
+            else:
+                pp = rng.integers(0, req.npix, 4)
+                qq = rng.integers(0, req.npix, 4)
+                got = o[torch.from_numpy(pp).to(o.device), torch.from_numpy(qq).to(o.device)].cpu().numpy()
+                ref = o1.adjoint(case["uvw"][r0:r1], case["freq"][:nch], req.data.cpu().numpy(), req.npix,
+                                 req.npix, req.pixsize, req.pixsize, pixels=(pp, qq))
+            worst = max(worst, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)) / req.epsilon)
+        out["oracle_check"] = {"requests_checked": len(reqs), "samples_each": 4, "max_rel_err_over_eps": worst}
+
+    checks.append(("serving", check))
+    return out
+
+
+def eps_sweep(case, dev, uvw, freq, n_vis, checks):
+    """Run time against requested accuracy (Sect. 6.3) on the wide-field
+    workload: for each epsilon the planner's kernel choice, then one degrid
+    and one grid timed after a warm-up of each.  FP32 where epsilon >= 1e-5,
+    FP64 from 1e-4 to 1e-12 (the paper runs both types).  The degridding
+    error against the direct sum on 1000 random visibilities is taken in the
+    accuracy leg at the end (``checks``)."""
+    import numpy as np
+    import torch
+
+    import paper_2010_10122_amd as wg
+    idx = np.random.default_rng(71).choice(n_vis, size=1000, replace=False)
+    idx_t = torch.from_numpy(idx).to(dev)
+    rows, samples = [], []
+    for prec, epss in (("f32", (1e-4, 3e-5, 1e-5)),
+                       ("f64", (1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12))):
+        rdt = torch.float32 if prec == "f32" else torch.float64
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        dirty = torch.from_numpy(case["dirty"]).to(dev, rdt)
+        vis = torch.from_numpy(case["vis"]).to(dev, cdt)
+        for eps in epss:
+            plan = wg.Plan(uvw, freq, case["npix_x"], case["npix_y"], case["pixsize_x"], case["pixsize_y"], eps,
+                           prec)
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+            out_v = plan.degrid(dirty, workspace=ws)
+            plan.grid(vis, workspace=ws)
+            t = {}
+            for name in ("degrid", "grid"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if name == "degrid":
+                    out_v = plan.degrid(dirty, workspace=ws)
+                else:
+                    plan.grid(vis, workspace=ws)
+                torch.cuda.synchronize()
+                t[name] = time.perf_counter() - t0
+            samples.append(out_v.reshape(-1)[idx_t].cpu().numpy())
+            info = plan.info
+            rows.append({"precision": prec, "epsilon": eps, "alpha": info["alpha"], "sigma": info["sigma"],
+                         "nu": info["nu"], "nw": info["nw"], "degrid_ms": round(t["degrid"] * 1e3, 1),
+                         "grid_ms": round(t["grid"] * 1e3, 1),
+                         "mvis_s": round(n_vis / (0.5 * (t["degrid"] + t["grid"])) / 1e6, 1),
+                         "whole_apply_hbm_frac": round(info["bytes_grid"] / (0.5 * (t["degrid"] + t["grid"])) /
+                                                       1e9 / HBM_PEAK_GBS, 4)})
+            print(f"[bench] eps sweep {prec} {eps:g}: {rows[-1]}", file=sys.stderr, flush=True)
+            plan.close()
+            del ws, out_v
+        del dirty, vis
+        torch.cuda.empty_cache()
+
+    def check():
+        import numpy as np
+
+        from oracle import o1
+        ref = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"], vis_idx=idx,
+                          pixels=np.nonzero(case["dirty"]))
+        for r, got in zip(rows, samples):
+            r["degrid_rel_err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    checks.append(("eps sweep", check))
+    return {"workload": "wide field (as the headline), one degrid + one grid per epsilon", "rows": rows}
+
+
+def paper_shape(dev, checks, steps=2):
+    """The benchmark set-up of Sect. 6 (synthetic stand-in for its MeerKAT
+    L-band set: 61 antennas, 824,476 rows x 2048 channels, flagged down to
+    about 470 million visibilities, 4096^2 over 1.6 deg):
+
+    * Sect. 6.1: FP32, eps = 1e-4, degrid and grid (plan build timed cold);
+    * Sect. 6.2: gridding and degridding without the w term, FP64,
+      eps = 1e-10, on the multi-channel set and on its flattened form (one
+      channel, one row per selected visibility).
+
+    Visibilities of the gridding legs are drawn on the device (seeded).  The
+    degridding error of each leg against the direct sum on 64 random
+    selected visibilities is taken in the accuracy leg (``checks``)."""
+    import numpy as np
+    import torch
+
+    import paper_2010_10122_amd as wg
+    import synth
+    t0 = time.perf_counter()
+    c = synth.meerkat_like()
+    n_vis = int(c["mask"].sum())
+    uvw = torch.from_numpy(c["uvw"]).to(dev)
+    freq = torch.from_numpy(c["freq"]).to(dev)
+    mask = torch.from_numpy(c["mask"]).to(dev)
+    print(f"[bench] paper shape: {c['uvw'].shape[0]} rows x {len(c['freq'])} ch, {n_vis} selected, "
+          f"generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    gen = torch.Generator(device=dev).manual_seed(61)
+    out = {"workload": (f"paper shape (Sect. 6): {c['uvw'].shape[0]} rows x {len(c['freq'])} ch, "
+                        f"{n_vis} selected vis, {c['npix_x']}^2 over 1.6 deg")}
+    sel = np.flatnonzero(c["mask"].reshape(-1))
+    pick = np.sort(np.random.default_rng(62).choice(sel, 64, replace=False))
+    samples = {}
+
+    def leg(name, uvw_, freq_, mask_, eps, prec, do_w, nv, idx):
+        rdt = torch.float32 if prec == "f32" else torch.float64
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = wg.Plan(uvw_, freq_, c["npix_x"], c["npix_y"], c["pixsize_x"], c["pixsize_y"], eps, prec,
+                       do_wgridding=do_w, mask=mask_)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        info = plan.info
+        dirty = torch.from_numpy(c["dirty"]).to(dev, rdt)
+        vis = torch.randn((plan.n_rows, plan.n_chan), dtype=cdt, device=dev, generator=gen)
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        out_v = plan.degrid(dirty, workspace=ws)
+        plan.grid(vis, workspace=ws)
+        t = {"degrid": 0.0, "grid": 0.0}
+        for _ in range(steps):
+            for d in ("degrid", "grid"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if d == "degrid":
+                    out_v = plan.degrid(dirty, workspace=ws)
+                else:
+                    plan.grid(vis, workspace=ws)
+                torch.cuda.synchronize()
+                t[d] += (time.perf_counter() - t0) / steps
+        samples[name] = out_v.reshape(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        r = {"precision": prec, "epsilon": eps, "w_gridding": do_w, "n_vis": nv, "alpha": info["alpha"],
+             "sigma": info["sigma"], "nu": info["nu"], "nw": info["nw"], "plan_ms": round(plan_s * 1e3, 1),
+             "degrid_ms": round(t["degrid"] * 1e3, 1), "grid_ms": round(t["grid"] * 1e3, 1),
+             "degrid_mvis_s": round(nv / t["degrid"] / 1e6, 1), "grid_mvis_s": round(nv / t["grid"] / 1e6, 1),
+             "mvis_s": round(nv / (0.5 * (t["degrid"] + t["grid"])) / 1e6, 1),
+             "degrid_over_grid": round(t["degrid"] / t["grid"], 3),
+             "whole_apply_hbm_frac": round(info["bytes_grid"] / (0.5 * (t["degrid"] + t["grid"])) / 1e9 /
+                                           HBM_PEAK_GBS, 4)}
+        print(f"[bench] {name}: {r}", file=sys.stderr, flush=True)
+        plan.close()
+        del vis, ws, dirty, out_v
+        torch.cuda.empty_cache()
+        return r
+
+    out["sect61_f32_eps1e-4"] = leg("sect61_f32_eps1e-4", uvw, freq, mask, 1e-4, "f32", True, n_vis, pick)
+    out["sect62_f64_eps1e-10_no_w"] = leg("sect62_f64_eps1e-10_no_w", uvw, freq, mask, 1e-10, "f64", False,
+                                          n_vis, pick)
+    # flattened: one row per selected visibility, uvw scaled to the first
+    # channel; the picked visibilities are rows searchsorted(sel, pick)
+    sel_t = torch.from_numpy(sel).to(dev)
+    rr = torch.div(sel_t, len(c["freq"]), rounding_mode="floor")
+    ch = sel_t - rr * len(c["freq"])
+    uvw_f = (uvw[rr] * (freq[ch] / freq[0])[:, None]).contiguous()
+    del sel_t, rr, ch
+    out["sect62_f64_eps1e-10_no_w_flat"] = leg("sect62_f64_eps1e-10_no_w_flat", uvw_f, freq[:1].contiguous(), None,
+                                               1e-10, "f64", False, n_vis, np.searchsorted(sel, pick))
+    del uvw_f, uvw, mask
+    torch.cuda.empty_cache()
+
+    def check():
+        import numpy as np
+
+        from oracle import o1
+        nz = np.nonzero(c["dirty"])
+        ref_w = o1.forward(c["uvw"], c["freq"], c["dirty"], c["pixsize_x"], c["pixsize_y"], vis_idx=pick, pixels=nz)
+        ref_nw = o1.forward(c["uvw"], c["freq"], c["dirty"], c["pixsize_x"], c["pixsize_y"], do_wgridding=False,
+                            vis_idx=pick, pixels=nz)
+        for name, ref in (("sect61_f32_eps1e-4", ref_w), ("sect62_f64_eps1e-10_no_w", ref_nw),
+                          ("sect62_f64_eps1e-10_no_w_flat", ref_nw)):
+            got = samples[name]
+            out[name]["degrid_rel_err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    checks.append(("paper shape", check))
+    return out
 
 
 def differentiation(dev, gd_steps=50, seed=5):
@@ -385,11 +628,19 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--dumps", type=int, default=2880, help="time dumps (2880 = the full 8 h workload)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
-    ap.add_argument("--large", action="store_true",
-                    help="also time the large workload (8192^2, 261M visibilities; adds about two minutes)")
-    ap.add_argument("--serve-requests", type=int, default=24,
-                    help="requests of the serving workload run after the operator timing (0 = skip)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large workload (8192^2, 261M visibilities; about two minutes)")
+    ap.add_argument("--no-eps-sweep", action="store_true", help="skip the run time against epsilon sweep")
+    ap.add_argument("--no-paper-shape", action="store_true", help="skip the Sect. 6 benchmark shape")
+    ap.add_argument("--serve-requests", type=int, default=60,
+                    help="requests of the serving workload, per load point (0 = skip)")
+    ap.add_argument("--quick", action="store_true",
+                    help="the FP32 headline only (no FP64, differentiation, serving, sweeps, large or CPU legs)")
     args = ap.parse_args()
+    if args.quick:
+        args.no_fp64 = args.no_diff = args.no_large = args.no_eps_sweep = args.no_paper_shape = True
+        args.no_cpu_baseline = True
+        args.serve_requests = 0
     if args.gpus != 1:
         print(f"bench.py: the operator runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -512,14 +763,20 @@ def main():
                      "nw": f["info"]["nw"], "plan_ms": round(f["plan_s"] * 1e3, 1), "steps": f["steps"]}
     if "fp64" in out:
         out["fp32_over_fp64"] = round(value / out["fp64"]["value"], 3)
-    if args.large:
-        out["large"] = large_workload(dev)
+    checks = []
     if not args.no_diff:
         out["differentiation"] = differentiation(dev)
     if args.serve_requests > 0:
-        out["serving"] = serving(case, args.serve_requests, dev)
-        out["serve_p50_ms"] = out["serving"]["poisson"]["p50_ms"]
-        out["serve_p99_ms"] = out["serving"]["poisson"]["p99_ms"]
+        out["serving"] = serving(case, args.serve_requests, dev, checks)
+        p08 = next(p for p in out["serving"]["poisson"] if p["offered_load"] == 0.8)
+        out["serve_p50_ms"] = p08["p50_ms"]
+        out["serve_p99_ms"] = p08["p99_ms"]
+    if not args.no_eps_sweep:
+        out["eps_sweep"] = eps_sweep(case, dev, uvw, freq, n_vis, checks)
+    if not args.no_paper_shape:
+        out["paper_shape"] = paper_shape(dev, checks)
+    if not args.no_large:
+        out["large"] = large_workload(dev)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(case, r["info"], n_vis)
@@ -527,11 +784,18 @@ def main():
         from oracle import o1
         for prec, rr in res.items():
             ref = o1.forward(case["uvw"], case["freq"], case["dirty"], case["pixsize_x"], case["pixsize_y"],
-                             vis_idx=rr["sample_idx"])
+                             vis_idx=rr["sample_idx"], pixels=np.nonzero(case["dirty"]))
             err = float(np.linalg.norm(rr["sample"] - ref) / np.linalg.norm(ref))
             (out if prec == "f32" else out["fp64" if prec == "f64" else "fp64_eps1e-10"])[
                 "degrid_rel_err_vs_oracle"] = err
-        print(f"[bench] cpu baseline in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        # the other legs' outputs against the oracle
+        for name, check in checks:
+            t1 = time.perf_counter()
+            check()
+            print(f"[bench] oracle check of {name} in {time.perf_counter() - t1:.1f} s", file=sys.stderr,
+                  flush=True)
+        print(f"[bench] cpu baseline and oracle checks in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
     prof.close()
     print(json.dumps(out), flush=True)
 

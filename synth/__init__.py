@@ -168,30 +168,36 @@ def differentiation(seed=5, n_dumps=620, n_chan=4, npix=1024, n_src=100, noise_f
                 sky=sky, noise_frac=noise_frac, rng=rng, name=f"diff-{npix}^2")
 
 
-def serving_requests(seed=4, count=32, sizes=(512, 1024, 2048, 4096), nvis_range=(1e5, 2e7),
+def serving_requests(seed=4, count=200, n_configs=12, sizes=(512, 1024, 2048, 4096), nvis_range=(1e5, 2e7),
                      epsilons=(1e-4, 1e-5, 1e-7, 1e-9), pixsize=10.0 * DEG / 2048, base=None):
-    """Request mix of the serving workload: image size uniform over ``sizes``;
-    visibility count log-uniform over ``nvis_range``, drawn as a contiguous
-    row range of the wide-field array (16 channels, fewer for small counts);
-    epsilon uniform over ``epsilons`` (FP32 where eps >= 1e-5, else FP64);
-    direction degrid/grid 50/50.  Returns (base workload, list of dicts)."""
+    """Request mix of the serving workload.  ``n_configs`` operator
+    configurations are drawn first (image size uniform over ``sizes``;
+    visibility count log-uniform over ``nvis_range``, as a contiguous row
+    range of the wide-field array with 16 channels, fewer for small counts;
+    epsilon uniform over ``epsilons``, FP32 where eps >= 1e-5, else FP64), then
+    ``count`` requests, each on a configuration drawn uniformly, direction
+    degrid/grid 50/50, with its own data seed.  Returns (base workload,
+    configurations, requests)."""
     rng = np.random.default_rng(seed)
     if base is None:
         base = wide_field(with_vis=False)
     nrow_all, nch_all = base["uvw"].shape[0], len(base["freq"])
-    out = []
-    for rid in range(count):
+    configs = []
+    for cid in range(n_configs):
         npix = int(rng.choice(sizes))
         nvis = int(10 ** rng.uniform(np.log10(nvis_range[0]), np.log10(nvis_range[1])))
         nch = int(min(nch_all, max(1, nvis // 20000)))
         nrow = int(min(nrow_all, max(1, nvis // nch)))
         r0 = int(rng.integers(0, nrow_all - nrow + 1))
         eps = float(rng.choice(epsilons))
-        out.append(dict(rid=rid, npix=npix, pixsize=pixsize, rows=(r0, r0 + nrow), nchan=nch, epsilon=eps,
-                        precision="f32" if eps >= 1e-5 else "f64",
-                        direction="degrid" if rng.random() < 0.5 else "grid",
-                        seed=int(rng.integers(0, 2 ** 31))))
-    return base, out
+        configs.append(dict(cid=cid, npix=npix, pixsize=pixsize, rows=(r0, r0 + nrow), nchan=nch, epsilon=eps,
+                            precision="f32" if eps >= 1e-5 else "f64"))
+    reqs = []
+    for rid in range(count):
+        c = configs[int(rng.integers(0, n_configs))]
+        reqs.append(dict(c, rid=rid, direction="degrid" if rng.random() < 0.5 else "grid",
+                         seed=int(rng.integers(0, 2 ** 31))))
+    return base, configs, reqs
 
 
 def meerkat_like(seed=6, n_dumps=436, n_chan=2048, npix=4096, fov_deg=1.6, n_src=1000, target_vis=470e6,
