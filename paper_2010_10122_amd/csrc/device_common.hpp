@@ -107,22 +107,32 @@ __device__ __forceinline__ VisCoord vis_coord(double u_m, double v_m, double w_m
 // from the piecewise polynomials of Sect. 4.2: every cell of an axis shares
 // the local variable z = 2 (offset + alpha/2) - 1 in [-1, 1), and cell i
 // uses its own coefficients (coef is degree-major: coef[d * ALPHA + i]).
-// One read of each coefficient row serves all three axes (3 alpha
-// independent Horner chains per step).
-template <int ALPHA, typename R>
-__device__ __forceinline__ void kernel_values_z3(R zu, R zv, R zw, const R *__restrict__ coef, int degree,
-                                                 R ku[ALPHA], R kv[ALPHA], R kw[ALPHA]) {
+// One read of each coefficient row serves all the axes (alpha independent
+// Horner chains per axis and step).  Without the w term (W false) only u
+// and v are evaluated and kw is the single plane's unit weight.
+template <int ALPHA, typename R, bool W>
+__device__ __forceinline__ void kernel_values(R zu, R zv, R zw, const R *__restrict__ coef, int degree,
+                                              R ku[ALPHA], R kv[ALPHA], R kw[ALPHA]) {
 #pragma unroll
-    for (int i = 0; i < ALPHA; ++i) ku[i] = kv[i] = kw[i] = coef[degree * ALPHA + i];
+    for (int i = 0; i < ALPHA; ++i) {
+        ku[i] = kv[i] = coef[degree * ALPHA + i];
+        kw[i] = W ? ku[i] : (R)(i == 0);
+    }
     for (int d = degree - 1; d >= 0; --d) {
 #pragma unroll
         for (int i = 0; i < ALPHA; ++i) {
             const R c = coef[d * ALPHA + i];
             ku[i] = ku[i] * zu + c;
             kv[i] = kv[i] * zv + c;
-            kw[i] = kw[i] * zw + c;
+            if (W) kw[i] = kw[i] * zw + c;
         }
     }
+}
+template <int ALPHA, typename R>
+__device__ __forceinline__ void kernel_values_z3(bool do_w, R zu, R zv, R zw, const R *__restrict__ coef,
+                                                 int degree, R ku[ALPHA], R kv[ALPHA], R kw[ALPHA]) {
+    if (do_w) kernel_values<ALPHA, R, true>(zu, zv, zw, coef, degree, ku, kv, kw);
+    else kernel_values<ALPHA, R, false>(zu, zv, zw, coef, degree, ku, kv, kw);
 }
 
 // sin and cos of 2 pi ph for ph in [-1/2, 1/2] (a phase in turns, already

@@ -432,7 +432,9 @@ double map_error_sup(int alpha, double sigma, double beta, double mu, bool refin
     std::vector<double> qt, qw;
     psi_nodes(alpha, beta, mu, qt, qw);
     const double xmax = 0.5 / sigma;
-    const int nx = 160;
+    // l(x) oscillates faster for wider kernels: the reported value samples
+    // the band more densely than the search's cheaper objective
+    const int nx = refine ? std::max(160, 48 * alpha) : 160;
     std::vector<double> xs(nx + 1), ls(nx + 1);
     for (int i = 0; i <= nx; ++i) {
         xs[i] = xmax * i / nx;

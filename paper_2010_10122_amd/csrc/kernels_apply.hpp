@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
             s_rec[tid] = rec;
             const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
             R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
+            kernel_values_z3<ALPHA, R>(g.do_w, zu, zv, zw, s_coef, a.degree, ku, kv, kw);
             R *pu = s_ku + tid * KP;
             R *pv = s_kv + tid * KP;
 #pragma unroll
@@ -602,7 +602,7 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
             footprint_masks<ALPHA>(in.an, A, B, g, la0, lb0, bm, cm);
             s_bs[tid] = make_int2(3 + tid * KP - la0, 3 + tid * KP - lb0);
             float ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, float>(in.zu, in.zv, g.do_w ? in.zw : 0.f, s_coef, a.degree, ku, kv, kw);
+            kernel_values_z3<ALPHA, float>(g.do_w, in.zu, in.zv, in.zw, s_coef, a.degree, ku, kv, kw);
             float *pu = s_ku + 3 + tid * KP;
             float *pv = s_kv + 3 + tid * KP;
 #pragma unroll
@@ -758,6 +758,12 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
         j_first = max(j_lo, iw0);
         j_hi = min(j_hi, iw1 + ALPHA);
     }
+    // Staging (FP32) copies window cell c = tid + k * 256 of each plane; its
+    // offset within a plane (the window wraps around the grid; N_u * N_v <
+    // 2^32 since the anchors hold 16 bits per axis) is formed once per
+    // group, not once per plane and cell.
+    constexpr int WW = W * W;
+    constexpr int KC = (WW + 255) / 256;
     // One visibility per thread and chunk: its inputs are read before the
     // chunk's first barrier, its kernel values once (while the first group
     // of planes is staged), and its sum is kept in registers over the
@@ -787,21 +793,41 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
             const int g1 = min(g0 + PD, j_hi);
             const int np = g1 - g0;
             if (g0 != j_first) __syncthreads();   // the previous group's readers are done
-            for (int e = tid; e < np * W * W; e += blockDim.x) {
-                const int p = e / (W * W), cell = e - p * (W * W);
-                const int ra = cell / W, rb = cell - ra * W;
-                int ga = A * kTileCells + ra;
-                int gb = B * kTileCells + rb;
-                if (ga >= g.nu) ga -= g.nu;
-                if (gb >= g.nv) gb -= g.nv;
-                st[e] = G[((int64_t)(g0 - j_lo + p) * g.nu + ga) * g.nv + gb];
+            if constexpr (sizeof(R) == 8) {
+                // FP64: the plain loop (the form below costs registers, and
+                // with them a wave per SIMD)
+                for (int e = tid; e < np * WW; e += 256) {
+                    const int p = e / WW, cell = e - p * WW;
+                    const int ra = cell / W, rb = cell - ra * W;
+                    int ga = A * kTileCells + ra;
+                    int gb = B * kTileCells + rb;
+                    if (ga >= g.nu) ga -= g.nu;
+                    if (gb >= g.nv) gb -= g.nv;
+                    st[e] = G[((int64_t)(g0 - j_lo + p) * g.nu + ga) * g.nv + gb];
+                }
+            } else {
+                uint32_t src_off[KC];
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int c = tid + k * 256;
+                    const int ra = c / W, rb = c - (c / W) * W;
+                    int ga = A * kTileCells + ra;
+                    int gb = B * kTileCells + rb;
+                    if (ga >= g.nu) ga -= g.nu;
+                    if (gb >= g.nv) gb -= g.nv;
+                    src_off[k] = (uint32_t)ga * (uint32_t)g.nv + (uint32_t)gb;
+                }
+                for (int p = 0; p < np; ++p) {
+                    const C *plane = G + (int64_t)(g0 - j_lo + p) * g.nu * g.nv;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) {
+                        const int c = tid + k * 256;
+                        if (k < KC - 1 || c < WW) st[p * WW + c] = plane[src_off[k]];
+                    }
+                }
             }
             if (g0 == j_first && act) {
-                kernel_values_z3<ALPHA, R>(zu, zv, g.do_w ? zw : (R)0, s_coef, a.degree, ku, kv, kw);
-                if (!g.do_w) {
-#pragma unroll
-                    for (int i = 0; i < ALPHA; ++i) kw[i] = (R)(i == 0);
-                }
+                kernel_values_z3<ALPHA, R>(g.do_w, zu, zv, zw, s_coef, a.degree, ku, kv, kw);
             }
             __syncthreads();
             const int jw0 = g.do_w ? max(iw, g0) : g0;
@@ -861,6 +887,17 @@ __global__ __launch_bounds__(256) void k_degrid(VisArgs<R> a, int J, int PD, con
 // ---------------------------------------------------------------------------
 // FFT passes.  Grid order: rows (contiguous, along v) then columns (along u).
 // ---------------------------------------------------------------------------
+// The intermediate T between the two passes of each direction is stored in
+// panels of kPanel columns: T[p][c / kPanel][r][c % kPanel] (r the row the
+// first pass transformed, c its retained output column).  A panel row is one
+// 128-byte line (FP32), so the first pass still writes whole lines, and the
+// K <= kPanel columns a column-pass workgroup reads lie in one panel, whose
+// rows follow each other in memory (not a 32-byte piece every row stride).
+constexpr int kPanel = 16;
+__host__ __device__ inline int64_t panel_elems(int cols, int rows) {
+    return (int64_t)((cols + kPanel - 1) / kPanel) * rows * kPanel;
+}
+
 struct PassGeom {
     int nu, nv, npix_x, npix_y;
     int P, nw;
@@ -879,7 +916,9 @@ __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, 
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int a = blockIdx.x, p = blockIdx.y;
     const C *src = G + ((int64_t)p * pg.nu + a) * pg.nv;
-    C *dst = T + ((int64_t)p * pg.nu + a) * pg.npix_y;
+    // row a of panel 0 of plane p; panel c holds columns c kPanel ..
+    C *dst = T + p * panel_elems(pg.npix_y, pg.nu) + (int64_t)a * kPanel;
+    const int64_t pstride = (int64_t)pg.nu * kPanel;
     const int h = pg.npix_y / 2;
     lds_fft<false, false, +1, NTH, false, CAP>(
         buf, 1, fd, tw, [&](int n, int) { return src[n]; },
@@ -887,7 +926,7 @@ __global__ __launch_bounds__(NTH) void k_rows_grid(const Cx<R> *__restrict__ G, 
             // output frequency o holds image column q with o = (q - h) mod N_v
             int q = o + h;
             if (q >= pg.nv) q -= pg.nv;
-            if (q < pg.npix_y) dst[q] = v;
+            if (q < pg.npix_y) dst[(q / kPanel) * pstride + (q % kPanel)] = v;
         });
 }
 
@@ -924,7 +963,8 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     };
     for (int e = threadIdx.x; e < ne; e += NTH) sum[e] = (R)0;
     for (int p = 0; p < np; ++p) {
-        const C *src = T + (int64_t)p * pg.nu * pg.npix_y;
+        // the K columns q0 .. lie in one panel (K divides kPanel)
+        const C *src = T + p * panel_elems(pg.npix_y, pg.nu) + (int64_t)(q0 / kPanel) * pg.nu * kPanel + q0 % kPanel;
         const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
         // an opaque copy of K per plane: otherwise every FFT address is
         // hoisted out of the plane loop and held in registers across it
@@ -933,7 +973,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
         lds_fft<false, true, +1, NTH, true>(
             buf, Kp, fd, tw,
             [&](int n, int col) {
-                return col < kk ? src[(int64_t)n * pg.npix_y + q0 + col] : cmake<C>((R)0, (R)0);
+                return col < kk ? src[(int64_t)n * kPanel + col] : cmake<C>((R)0, (R)0);
             },
             NoIo{});
         for (int e = threadIdx.x; e < ne; e += NTH) {
@@ -983,7 +1023,9 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
     {
         const int p = blockIdx.y;
         const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
-        C *dst = T + ((int64_t)p * pg.npix_x + row) * pg.nv;
+        // row `row` of panel 0 of plane p; panel c holds grid columns c kPanel ..
+        C *dst = T + p * panel_elems(pg.nv, pg.npix_x) + (int64_t)row * kPanel;
+        const int64_t pstride = (int64_t)pg.npix_x * kPanel;
         for (int b = threadIdx.x; b < pg.nv; b += NTH) {
             // grid position b holds image column q with b = (q - h) mod N_v
             const int q = b < pg.nv - h ? b + h : b - (pg.nv - h);
@@ -1004,7 +1046,9 @@ __global__ __launch_bounds__(NTH) void k_rows_degrid(const R *__restrict__ itil,
             buf[fft_lidx(b)] = v;
         }
         __syncthreads();
-        lds_fft<true, false, -1, NTH, false, CAP>(buf, 1, fd, tw, NoIo{}, [&](int o, int, C v, int) { dst[o] = v; });
+        lds_fft<true, false, -1, NTH, false, CAP>(buf, 1, fd, tw, NoIo{}, [&](int o, int, C v, int) {
+            dst[(o / kPanel) * pstride + (o % kPanel)] = v;
+        });
     }
 }
 
@@ -1025,7 +1069,8 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
     const int p = blockIdx.y;
     const int kk = min(K, pg.nv - b0);
     const int h = pg.npix_x / 2;
-    const C *src = T + (int64_t)p * pg.npix_x * pg.nv;
+    // the K columns b0 .. lie in one panel (K divides kPanel)
+    const C *src = T + p * panel_elems(pg.nv, pg.npix_x) + (int64_t)(b0 / kPanel) * pg.npix_x * kPanel + b0 % kPanel;
     C *dst = G + (int64_t)p * pg.nu * pg.nv;
     lds_fft<false, false, -1, NTH, true, CAP>(
         buf, K, fd, tw,
@@ -1034,7 +1079,7 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
             int pp = -1;
             if (a < pg.npix_x - h) pp = a + h;
             else if (a >= pg.nu - h) pp = a - (pg.nu - h);
-            return (pp >= 0 && col < kk) ? src[(int64_t)pp * pg.nv + b0 + col] : cmake<C>((R)0, (R)0);
+            return (pp >= 0 && col < kk) ? src[(int64_t)pp * kPanel + col] : cmake<C>((R)0, (R)0);
         },
         [&](int o, int col, C v, int) {
             if (col < kk) dst[(int64_t)o * pg.nv + b0 + col] = v;

@@ -34,11 +34,15 @@ template <typename R, int ALPHA> struct Launch {
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        if constexpr (sizeof(R) == 4) {      // FP32: matrix cores
-            if (p->P > 4)
+        if constexpr (sizeof(R) == 4) {      // FP32: matrix cores, except for a single plane (no w
+            if (p->P == 1)                   // term), where 14 of their 16 plane-value rows would be idle
+                grid_ps<1>(p, va, J, G, part, st);
+            else if (p->P > 4)
                 grid_mx<8>(p, va, J, G, part, st);
             else
                 grid_mx<4>(p, va, J, G, part, st);
+        } else if (p->P == 1) {              // one plane (no w term): one accumulator slot
+            grid_ps<1>(p, va, J, G, part, st);
         } else {
             grid_ps<4>(p, va, J, G, part, st);
         }

@@ -403,7 +403,7 @@ size_t plan_layout(wg_plan *p, int64_t slots) {
     p->off_G = off;
     off = align(off + (size_t)p->P * g.nu * g.nv * sc);
     p->off_T = off;
-    off = align(off + (size_t)p->P * std::max((size_t)g.nu * g.npix_y, (size_t)g.npix_x * g.nv) * sc);
+    off = align(off + (size_t)p->P * std::max(panel_elems(g.npix_y, g.nu), panel_elems(g.nv, g.npix_x)) * sc);
     p->off_acc = off;
     off = align(off + (size_t)npix * sr);
     p->off_itil = off;
@@ -550,11 +550,15 @@ int plan_host(wg_plan *p) {
     const size_t lds_cap = 160 * 1024;
     if ((size_t)std::max(g.nu, g.nv) * sc > lds_cap || std::max(g.nu, g.nv) > max_grid(d.precision))
         return WG_EUNSUPPORTED;
-    // columns per workgroup in the strided passes: fill up to 96 KB of LDS
-    // (FP32 <= 12288 values = 512 threads x kFftMaxC, FP64 <= 6144 = 256 x kFftMaxC)
+    // columns per workgroup in the strided passes: as many as fit about
+    // 144 KB of LDS (the gridding column pass also keeps npix_x * K image
+    // sums there) and the values one column-pass workgroup transforms, N K:
+    // FP32 <= 12288 (1024 threads x 12), FP64 <= 6144 (256 threads x
+    // kFftMaxC), the same bounds that cap N itself
+    const int64_t col_values = d.precision == WG_F32 ? 12288 : 6144;
     p->k_cols = 1;
-    // (the gridding column pass also keeps npix_x * K image sums in LDS)
-    while (p->k_cols < 8 && (size_t)(fft_lds_len(g.nu) * sc + d.npix_x * sr) * (2 * p->k_cols) <= 144 * 1024)
+    while (p->k_cols < 8 && (size_t)(fft_lds_len(g.nu) * sc + d.npix_x * sr) * (2 * p->k_cols) <= 144 * 1024 &&
+           (int64_t)g.nu * 2 * p->k_cols <= col_values)
         p->k_cols *= 2;
     p->k_cols_d = p->k_cols;
     // planes per batch: the gridder keeps one register accumulator per plane

@@ -191,7 +191,14 @@ def test_small_plain_vs_direct(dev, prec, eps):
     ev, ei = rel(res["vis"], d1), rel(res["img"], i1)
     print(f"   plan {res['info']['alpha']}/{res['info']['sigma']}: degrid {ev:.2e} grid {ei:.2e}")
     assert ev < eps and ei < eps
-    assert K.feasible(res["info"]["alpha"], res["info"]["sigma"], eps, True)
+    info = res["info"]
+    # the kernel meets eps: by the printed accuracy, or by the oracle's map
+    # error for a searched row
+    if info["alpha"] in K.TABLE and any(abs(r[0] - info["sigma"]) < 1e-9 for r in K.TABLE[info["alpha"]]):
+        assert K.feasible(info["alpha"], info["sigma"], eps, True)
+    else:
+        ek = K.kernel_accuracy(info["alpha"], info["sigma"], info["beta"], info["mu"], nx=2049)
+        assert K.error_factor(True) * ek <= 1.03 * eps
     res["plan"].close()
 
 
@@ -309,7 +316,7 @@ def test_invalid_arguments(dev):
         with pytest.raises(wg.WgridError):
             wg.Plan(uvw, freq, kw.get("npix_x", 64), 64, pix, pix, kw.get("eps", 1e-5), kw.get("prec", "f32"))
     with pytest.raises(wg.WgridError):
-        wg.Plan(uvw, freq, 64, 64, case["pixsize_x"], case["pixsize_y"], 1e-5, "f32", alpha=12, sigma=1.85)
+        wg.Plan(uvw, freq, 64, 64, case["pixsize_x"], case["pixsize_y"], 1e-5, "f32", alpha=12, sigma=1.83)
 
 
 @pytest.mark.parametrize("which", ["small", "multichan", "masked"])
@@ -327,3 +334,38 @@ def test_grid_stream_order(dev, which):
         n = check_grid_order(case, res["plan"], torch, mask)
         print(f"[grid order] {which} {prec}: {n} visibilities", flush=True)
         res["plan"].close()
+
+
+@pytest.mark.parametrize("npix,sigma,prec", [(3584, 1.8, "f32"), (4096, 1.6, "f32"), (3584, 1.9, "f32"),
+                                             (4096, 1.5, "f64")])
+def test_large_fft_lengths_vs_direct(dev, npix, sigma, prec):
+    """Grid lengths just above 6144 (6480, 6720, 6912 FP32; 6144 FP64): the
+    column passes' block width must keep N K within what one workgroup's
+    transform holds.  A few point sources and 16,000 visibilities, both
+    directions against the direct sum on samples."""
+    import paper_2010_10122_amd as wg
+    rng = np.random.default_rng(npix + int(100 * sigma))
+    c = synth.meerkat_like(n_dumps=4, n_chan=8, with_mask=False)
+    uvw_h, freq_h = c["uvw"][:2000], c["freq"]
+    pix = 1.6 * math.pi / 180 / 4096
+    eps = 1e-4
+    plan = wg.Plan(torch.from_numpy(uvw_h).to(dev), torch.from_numpy(freq_h).to(dev), npix, npix, pix, pix, eps,
+                   prec, alpha=7, sigma=sigma)
+    info = plan.info
+    print(f"[long fft] {prec} N={info['nu']} Nw={info['nw']}", flush=True)
+    rdt = plan.real_dtype
+    dirty = np.zeros((npix, npix))
+    dirty[rng.integers(0, npix, 12), rng.integers(0, npix, 12)] = rng.random(12) + 0.5
+    vis = plan.degrid(torch.from_numpy(dirty).to(dev, rdt)).cpu().numpy()
+    idx = rng.choice(vis.size, 300, replace=False)
+    ref = o1.forward(uvw_h, freq_h, dirty, pix, pix, vis_idx=idx, pixels=np.nonzero(dirty))
+    e_deg = rel(vis.reshape(-1)[idx], ref)
+    v_in = synth.complex_gaussian(rng, vis.shape)
+    img = plan.grid(torch.from_numpy(v_in).to(dev, plan.complex_dtype)).cpu().numpy()
+    pp, qq = rng.integers(0, npix, 24), rng.integers(0, npix, 24)
+    ref_i = o1.adjoint(uvw_h, freq_h, v_in, npix, npix, pix, pix, pixels=(pp, qq))
+    e_grid = rel(img[pp, qq], ref_i)
+    print(f"   degrid {e_deg:.2e} grid {e_grid:.2e}", flush=True)
+    assert np.isfinite(vis).all() and np.isfinite(img).all()
+    assert e_deg < eps and e_grid < eps
+    plan.close()
