@@ -295,11 +295,20 @@ double max_abs_nm1(int npix_x, int npix_y, double pixsize_x, double pixsize_y) {
 // Rates are nominal MI355X figures (effective HBM and LDS-update throughput).
 double predict_seconds(int alpha, double sigma, int precision, int do_w, int npix_x, int npix_y,
                        double max_nm1, int64_t n_vis, double wmin, double wmax) {
+    // Mean time of one application (degridding and gridding averaged),
+    // calibrated on this library's kernels with the wide-field workload
+    // (2048^2, 92.9 million visibilities) over the kernels the planner
+    // chose between 1e-4 and 1e-12:
+    // * per w-plane: the plane traffic of the two FFT passes and of the
+    //   visibility kernels, at an effective 4.0 TB/s (FP32) / 1.6 TB/s
+    //   (FP64), plus launch tails;
+    // * per visibility, with w-gridding: FP32 0.27 ns + 0.205 ps alpha^3,
+    //   FP64 1.14 ps alpha^3 (the gather/accumulate over alpha^3 cells);
+    //   without w: 1.4 ps (FP32) / 2.8 ps (FP64) alpha^2.
     const double sc = precision == 0 ? 8.0 : 16.0;
     const double sr = sc * 0.5;
-    const double hbm = 5.0e12;              // B/s achieved by streaming kernels
-    const double upd = precision == 0 ? 3.0e12 : 1.5e12;   // LDS complex updates/s
-    const double per_plane_overhead = 6e-6; // launches and tails per plane
+    const double bw = precision == 0 ? 4.0e12 : 1.6e12;
+    const double per_plane_overhead = 2e-6;
     int nu = grid_size(sigma, npix_x), nv = grid_size(sigma, npix_y);
     double nw = 1.0;
     if (do_w) {
@@ -308,11 +317,12 @@ double predict_seconds(int alpha, double sigma, int precision, int do_w, int npi
     }
     double plane_bytes = (double)nu * nv * sc * 2.0 + (double)nu * npix_y * sc * 2.0 +
                          2.0 * (double)npix_x * npix_y * sr;
-    double t_planes = nw * (plane_bytes / hbm + per_plane_overhead);
-    double cells = do_w ? (double)alpha * alpha * alpha : (double)alpha * alpha;
-    double owner = (16.0 + alpha - 1) * (16.0 + alpha - 1) / 256.0;   // halo redundancy
-    double t_vis = (double)n_vis * (cells / upd + owner * alpha * 40.0 / 6e12);
-    return t_planes + t_vis;
+    double t_planes = nw * (plane_bytes / bw + per_plane_overhead);
+    const double a2 = (double)alpha * alpha, a3 = a2 * alpha;
+    double per_vis;
+    if (do_w) per_vis = precision == 0 ? 2.7e-10 + 2.05e-13 * a3 : 1.14e-12 * a3;
+    else per_vis = (precision == 0 ? 1.4e-12 : 2.8e-12) * a2;
+    return t_planes + (double)n_vis * per_vis;
 }
 
 // Root-mean-square over the image of Psi(0)/Psi(l, m): the factor by which

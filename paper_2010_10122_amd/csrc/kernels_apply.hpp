@@ -10,7 +10,7 @@ namespace wg {
 constexpr int kTileCells = 16;            // uv tile edge (cells)
 constexpr int kTileArea = kTileCells * kTileCells;
 #ifndef WG_GRID_ITEM_CAP
-#define WG_GRID_ITEM_CAP 2048
+#define WG_GRID_ITEM_CAP 512
 #endif
 constexpr int kGridItemCap = WG_GRID_ITEM_CAP;   // visibilities per gridder work item
 constexpr int kDegridItemCap = 512;              // visibilities per degridder work item (one per thread)
@@ -274,62 +274,6 @@ __device__ __forceinline__ void build_region_lists(int bm, int cm, int tid, int 
     __syncthreads();
 }
 
-// The same lists packed back to back: region r's list starts at base_r, the
-// sum of the padded lengths of the regions before it, so the capacity is
-// CH times the most regions one footprint meets (not 16 CH).  Returns, in
-// lane r (r = lane mod 16), base_r.  Ends with a barrier.
-template <int CH, int PAD>
-__device__ __forceinline__ int build_region_lists_packed(int bm, int cm, int tid, int lane, int wave, int *s_cnt,
-                                                         uint16_t *s_list) {
-    unsigned long long balr[4], balc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        balr[q] = __ballot((bm >> q) & 1);
-        balc[q] = __ballot((cm >> q) & 1);
-    }
-    if (lane < 16) {
-        const int qr = lane >> 2, qc = lane & 3;
-        unsigned long long br = balr[0], bc = balc[0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            br = qr == q ? balr[q] : br;
-            bc = qc == q ? balc[q] : bc;
-        }
-        s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
-    }
-    __syncthreads();
-    // lane r: region r's total, this wave's offset in it, padded length, base
-    const int r = lane & 15;
-    const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + r * 4);
-    const int tot = c4.x + c4.y + c4.z + c4.w;
-    const int woff = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
-    const int len = ((tot + 3) & ~3) + PAD;
-    int base = 0;
-#pragma unroll
-    for (int rr = 0; rr < 15; ++rr) {
-        const int l = __builtin_amdgcn_readlane(len, rr);
-        base += rr < r ? l : 0;
-    }
-    const int start = base + woff;
-#pragma unroll
-    for (int rg = 0; rg < 16; ++rg) {
-        const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
-        const int off = __builtin_amdgcn_readlane(start, rg);
-        const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
-        if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[at] = (uint16_t)tid;
-    }
-    {
-        // thread tid pads region tid / 16 (16 threads a region)
-        const int rg = tid >> 4, k = tid & 15;
-        const int b = __shfl(base, rg), n = __shfl(tot, rg);
-        static_assert(PAD + 3 <= 16, "padding per region");
-        if (n + k < ((n + 3) & ~3) + PAD) s_list[b + n + k] = (uint16_t)CH;
-    }
-    __syncthreads();
-    return base;
-}
-
 template <typename R, int ALPHA, int PS>
 __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra,
                                               int cap, Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
@@ -486,8 +430,8 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 }
 
 // ---------------------------------------------------------------------------
-// FP32 gridder on the matrix cores.  Same tiles, items, chunks and region
-// lists as k_grid; phase 2 is a matrix product per region.  For the four
+// FP32 gridder on the matrix cores.  Same tiles and items as k_grid;
+// phase 2 is a matrix product per region.  For the four
 // visibilities k of a step and the 16 cells m of a region,
 //     D[n][m] += sum_k  dk_k[n] * (ku_k[row m] kv_k[col m]),
 // where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility (its
@@ -499,47 +443,51 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 // of planes 2 (l / 16) and 2 (l / 16) + 1.  The u and v kernel rows sit
 // back to back with three zeros between them (the zeros after a row are the
 // next row's leading ones), so every cell of a region the footprint meets
-// indexes a kernel value or a zero.  The region lists are packed back to
-// back; with these records four workgroups share a CU (LDS, and at most 128
-// registers a lane).
+// indexes a kernel value or a zero.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int ALPHA> struct GridStageMx {
-    static constexpr int CH = 256;                 // visibilities per chunk
-    static constexpr int S = CH + 1;               // + the zero padding slot
-    static constexpr int KP = ALPHA + 3;           // kernel row + the gap before the next one
-    static constexpr int NKP = (S + 1) * KP + 16;  // rows 0..CH (row CH all zero) + zero tail
-    static constexpr int NW = 8;                   // w weights per visibility (plane slots)
-    static constexpr int RPA = (ALPHA + 6) / 4 < 4 ? (ALPHA + 6) / 4 : 4;   // regions a footprint meets per axis
-    static constexpr int PAD = 4;                  // list entries read ahead
-    static constexpr int LSTT = (CH * RPA * RPA + 16 * (3 + PAD) + 15) & ~15;   // packed list capacity
+// Gridder, FP32 on the matrix cores (adjoint, eqs. Rad2 / R2 bracket).
+// One 64-lane workgroup per work item (a tile and batch, or a share of a
+// long tile list): the wave owns all 16 4x4-cell regions of its tile, 16
+// accumulators of 4 values a lane, so no other wave takes part in a chunk.
+// Per chunk of 64 visibilities of the tile's nine stream runs: phase 1 one
+// lane per visibility (kernel values, rotated w weights, footprint
+// masks) into LDS; region lists from the wave's ballots; phase 2 one
+// v_mfma_f32_16x16x4_f32 per region and four listed visibilities, two
+// regions at a time (see the design notes for the operand layout).  168
+// registers: three waves a SIMD (four would spill).
+template <int ALPHA> struct GridStageMx1 {
+    static constexpr int CH = 64;
+    static constexpr int S = CH + 1;
+    static constexpr int KP = ALPHA + 3;
+    static constexpr int NKP = (S + 1) * KP + 16;
+    static constexpr int NW = 8;
+    static constexpr int LST = CH + 8;             // per-region list: entries + padding
     static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
     static constexpr size_t off_kv = al((size_t)NKP * sizeof(float));
     static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(float));
     static constexpr size_t off_d = al(off_kw + (size_t)S * NW * sizeof(float));
     static constexpr size_t off_bs = al(off_d + (size_t)S * sizeof(float2));
     static constexpr size_t off_list = al(off_bs + (size_t)S * sizeof(int2));
-    static constexpr size_t off_cnt = al(off_list + (size_t)LSTT * sizeof(uint16_t));
-    static constexpr size_t off_coef = al(off_cnt + (size_t)16 * 4 * sizeof(int));
+    static constexpr size_t off_coef = al(off_list + (size_t)16 * LST);
     static constexpr size_t bytes = off_coef + kCoefBytes<float, ALPHA>;
 };
 
 template <int ALPHA, int PS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ALPHA <= 8 ? 4 : 1)))
-void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
-               float2 *__restrict__ G, float2 *__restrict__ part) {
-    using ST = GridStageMx<ALPHA>;
-    constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
+                float2 *__restrict__ G, float2 *__restrict__ part) {
+    using ST = GridStageMx1<ALPHA>;
+    constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW, LST = ST::LST;
     static_assert(PS <= NW, "one w weight per plane slot");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *s_ku = reinterpret_cast<float *>(smem_raw);                 // row v at 3 + v KP
+    float *s_ku = reinterpret_cast<float *>(smem_raw);
     float *s_kv = reinterpret_cast<float *>(smem_raw + ST::off_kv);
-    float *s_kw = reinterpret_cast<float *>(smem_raw + ST::off_kw);    // [S][NW] w weights on the plane slots
-    float *s_d = reinterpret_cast<float *>(smem_raw + ST::off_d);      // [S][2] weighted value
-    int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);      // [S] row bases into s_ku / s_kv
-    uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);
-    int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);
+    float *s_kw = reinterpret_cast<float *>(smem_raw + ST::off_kw);
+    float *s_d = reinterpret_cast<float *>(smem_raw + ST::off_d);
+    int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);
+    uint8_t *s_list = reinterpret_cast<uint8_t *>(smem_raw + ST::off_list);
     float *s_coef = reinterpret_cast<float *>(smem_raw + ST::off_coef);
 
     const Geom &g = a.g;
@@ -547,18 +495,14 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
     if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
     const int tile = item.x;
     const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int kv_of = lane >> 4, m = lane & 15;                // visibility of the step, region cell
-    const int row = 4 * wave + (m >> 2);                       // this lane's tile row
-    const int cc = m & 3;
+    const int lane = threadIdx.x;
+    const int kv_of = lane >> 4, m = lane & 15;
+    const int mr = m >> 2, cc = m & 3;
     const int j_lo = J * a.P;
     const int j_hi = min(j_lo + a.P, g.nw);
     const TileBins tb = tile_bins(a, J, A, B);
     const uint32_t first = (uint32_t)item.y;
     const uint32_t last = min(tb.total, first + (uint32_t)item.z);
-    // Inputs of a chunk position (anchor, weighted value, kernel-local
-    // coordinates) are read one chunk ahead: the first chunk's before the
-    // set-up barrier, the next chunk's while the current one accumulates.
     struct In {
         int2 an;
         float2 d;
@@ -575,43 +519,37 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
         return r;
     };
     In in{};
-    if (first + tid < last) in = load_in(first + tid);
-    // zero kernel rows and gaps (rows only ever overwrite their own ALPHA
-    // values), the zero slot's value, w weights and row bases, the
-    // coefficient table
-    for (int e = tid; e < ST::NKP; e += CH) {
+    if (first + lane < last) in = load_in(first + lane);
+    for (int e = lane; e < ST::NKP; e += CH) {
         s_ku[e] = 0.f;
         s_kv[e] = 0.f;
     }
-    if (tid < NW) s_kw[CH * NW + tid] = 0.f;
-    if (tid < 2) s_d[CH * 2 + tid] = 0.f;
-    if (tid == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
-    for (int e = tid; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
-    f32x4 acc[4];
+    if (lane < NW) s_kw[CH * NW + lane] = 0.f;
+    if (lane < 2) s_d[CH * 2 + lane] = 0.f;
+    if (lane == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
+    for (int e = lane; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
+    f32x4 acc[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 16; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
 
     for (uint32_t base = first; base < last; base += CH) {
-        // ---- phase 1: one thread per visibility -------------------------
-        const uint32_t pos = base + tid;
+        const uint32_t pos = base + lane;
         int bm = 0, cm = 0;
         if (pos < last) {
             const int iw = in.an.y & 0x7fffffff;
             int la0, lb0;
             footprint_masks<ALPHA>(in.an, A, B, g, la0, lb0, bm, cm);
-            s_bs[tid] = make_int2(3 + tid * KP - la0, 3 + tid * KP - lb0);
+            s_bs[lane] = make_int2(3 + lane * KP - la0, 3 + lane * KP - lb0);
             float ku[ALPHA], kv[ALPHA], kw[ALPHA];
             kernel_values_z3<ALPHA, float>(g.do_w, in.zu, in.zv, in.zw, s_coef, a.degree, ku, kv, kw);
-            float *pu = s_ku + 3 + tid * KP;
-            float *pv = s_kv + 3 + tid * KP;
+            float *pu = s_ku + 3 + lane * KP;
+            float *pv = s_kv + 3 + lane * KP;
 #pragma unroll
             for (int i = 0; i < ALPHA; ++i) {
                 pu[i] = ku[i];
                 pv[i] = kv[i];
             }
-            // plane slot rr holds plane j_lo + rr, kernel cell j_lo + rr - iw
-            // (slots past the last plane of the batch are never stored)
             float ws[PS];
             if (g.do_w) {
                 rotate_w<float, ALPHA, PS>(kw, j_lo - iw, ws);
@@ -619,7 +557,7 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
 #pragma unroll
                 for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? 1.f : 0.f;
             }
-            float4 *pw = reinterpret_cast<float4 *>(s_kw + tid * NW);
+            float4 *pw = reinterpret_cast<float4 *>(s_kw + lane * NW);
 #pragma unroll
             for (int n = 0; n < NW / 4; ++n) {
                 const int r0 = 4 * n;
@@ -627,31 +565,52 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
                                     r0 + 2 < PS ? ws[r0 + 2 < PS ? r0 + 2 : 0] : 0.f,
                                     r0 + 3 < PS ? ws[r0 + 3 < PS ? r0 + 3 : 0] : 0.f);
             }
-            reinterpret_cast<float2 *>(s_d)[tid] = in.d;
+            reinterpret_cast<float2 *>(s_d)[lane] = in.d;
         }
-        const int lbase = build_region_lists_packed<CH, ST::PAD>(bm, cm, tid, lane, wave, s_cnt, s_list);
-        if (base + CH + tid < last) in = load_in(base + CH + tid);
-        // ---- phase 2: one matrix product step per four visibilities ------
-        // Two regions at a time (two independent accumulator chains and
-        // twice the reads in flight); the shorter list reads the zero slot
-        // (its padding entry at index n4) once it is exhausted.
+        // region lists from the wave's ballots: region rg holds, in lane
+        // order, the slots whose footprint meets it, padded with the zero
+        // slot up to a multiple of 4 plus the 4 entries read ahead
+        unsigned long long balr[4], balc[4];
 #pragma unroll
-        for (int qp = 0; qp < 2; ++qp) {
+        for (int q = 0; q < 4; ++q) {
+            balr[q] = __ballot((bm >> q) & 1);
+            balc[q] = __ballot((cm >> q) & 1);
+        }
+        int cnt[16];
+#pragma unroll
+        for (int rg = 0; rg < 16; ++rg) {
+            const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
+            cnt[rg] = __popcll(bal);
+            const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[rg * LST + at] = (uint8_t)lane;
+        }
+        {
+            // lanes 4 rg .. 4 rg + 3 pad region rg, two entries each
+            const int rg = lane >> 2, k0 = (lane & 3) * 2;
+            int n = cnt[0];
+#pragma unroll
+            for (int q = 1; q < 16; ++q) n = rg == q ? cnt[q] : n;
+            const int end = ((n + 3) & ~3) + 4;
+            if (n + k0 < end) s_list[rg * LST + n + k0] = (uint8_t)CH;
+            if (n + k0 + 1 < end) s_list[rg * LST + n + k0 + 1] = (uint8_t)CH;
+        }
+        __syncthreads();
+        if (base + CH + lane < last) in = load_in(base + CH + lane);
+#pragma unroll
+        for (int qp = 0; qp < 8; ++qp) {
             const int qa = 2 * qp, qb = 2 * qp + 1;
-            const int rga = wave * 4 + qa, rgb = rga + 1;
-            const int4 ca = *reinterpret_cast<const int4 *>(s_cnt + rga * 4);
-            const int4 cb = *reinterpret_cast<const int4 *>(s_cnt + rgb * 4);
-            const int n4a = __builtin_amdgcn_readfirstlane((ca.x + ca.y + ca.z + ca.w + 3) & ~3);
-            const int n4b = __builtin_amdgcn_readfirstlane((cb.x + cb.y + cb.z + cb.w + 3) & ~3);
+            const int n4a = (cnt[qa] + 3) & ~3, n4b = (cnt[qb] + 3) & ~3;
             const int n4 = max(n4a, n4b);
-            const uint16_t *lsta = s_list + __builtin_amdgcn_readlane(lbase, rga) + kv_of;
-            const uint16_t *lstb = s_list + __builtin_amdgcn_readlane(lbase, rgb) + kv_of;
-            const int cola = 4 * qa + cc, colb = 4 * qb + cc;
+            const uint8_t *lsta = s_list + qa * LST + kv_of;
+            const uint8_t *lstb = s_list + qb * LST + kv_of;
+            const int rowa = 4 * (qa >> 2) + mr, cola = 4 * (qa & 3) + cc;
+            const int rowb = 4 * (qb >> 2) + mr, colb = 4 * (qb & 3) + cc;
             unsigned va = lsta[0], vb = lstb[0];
             int2 bsa = s_bs[va], bsb = s_bs[vb];
             for (int j = 0; j < n4; j += 4) {
-                const float kua = s_ku[bsa.x + row], kva = s_kv[bsa.y + cola];
-                const float kub = s_ku[bsb.x + row], kvb = s_kv[bsb.y + colb];
+                const float kua = s_ku[bsa.x + rowa], kva = s_kv[bsa.y + cola];
+                const float kub = s_ku[bsb.x + rowb], kvb = s_kv[bsb.y + colb];
                 const float ava = s_d[2 * va + (m & 1)] * s_kw[va * NW + (m >> 1)];
                 const float avb = s_d[2 * vb + (m & 1)] * s_kw[vb * NW + (m >> 1)];
                 unsigned vna = lsta[min(j + 4, n4a)], vnb = lstb[min(j + 4, n4b)];
@@ -667,12 +626,11 @@ void k_grid_mx(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_ex
         }
         __syncthreads();
     }
-    // lane l holds cell m of region q for planes 2 (l / 16) and 2 (l / 16) + 1
     const int np = j_hi - j_lo;
     const int r0 = 2 * kv_of;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int colw = 4 * q + cc;
+    for (int q = 0; q < 16; ++q) {
+        const int row = 4 * (q >> 2) + mr, colw = 4 * (q & 3) + cc;
         float2 *dst;
         int64_t pstride;
         if (item.w < 0) {

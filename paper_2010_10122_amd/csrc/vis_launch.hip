@@ -29,8 +29,8 @@ template <typename R, int ALPHA> struct Launch {
     static void grid_mx(const wg_plan *p, const VisArgs<float> &va, int J, float2 *G, float2 *part,
                         hipStream_t st) {
         const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
-        const size_t lds = GridStageMx<ALPHA>::bytes;
-        hipLaunchKernelGGL((k_grid_mx<ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
+        const size_t lds = GridStageMx1<ALPHA>::bytes;
+        hipLaunchKernelGGL((k_grid_mx1<ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(64), lds, st, va, J,
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
