@@ -63,8 +63,11 @@ struct wg_profiler {
             pool.pop_back();
             return e;
         }
+        // timing only: no system-scope fence at the event (that fence writes
+        // back and invalidates the caches at every kernel boundary, which
+        // both slows the next kernel and adds to the measured interval)
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
