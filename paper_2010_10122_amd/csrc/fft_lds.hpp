@@ -303,6 +303,25 @@ template <int RADIX, typename C> __device__ __forceinline__ void tw_powers(const
 // <= NTH * kFftMaxC.  A smaller CAP keeps fewer registers per pass.
 template <int NTH, int CAP> constexpr int fft_cap() { return CAP > 0 ? CAP : (NTH >= 512 ? 12288 / NTH : kFftMaxC); }
 
+// Butterfly indices without integer division: the column count K is a
+// power of two (a shift and a mask), and j mod Ns comes from the FP32
+// reciprocal of Ns.  For j < 2^20, (j + 1/2) / Ns lies at least 1/(2 Ns) from
+// an integer, and the rounding of 1/Ns and of the product (together below
+// 1.5 2^-23 relative) moves it by less than 2^20 / Ns * 1.5 2^-23 < 1/(4 Ns),
+// so the truncated quotient is exact.
+struct FftIdx {
+    int kshift, kmask, ns;
+    float rns;
+    __device__ __forceinline__ FftIdx(int K, int Ns)
+        : kshift(__builtin_ctz((unsigned)K)), kmask(K - 1), ns(Ns), rns(1.0f / (float)Ns) {}
+    __device__ __forceinline__ int row(int w) const { return w >> kshift; }
+    __device__ __forceinline__ int col(int w) const { return w & kmask; }
+    __device__ __forceinline__ int mod_ns(int j) const {
+        const int q = (int)(((float)j + 0.5f) * rns);
+        return j - q * ns;
+    }
+};
+
 template <int RADIX, int DIR, int NTH, bool first, bool last, bool PF, int CAP, typename C, typename Load,
           typename Store>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *__restrict__ tw, Load &load,
@@ -313,6 +332,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
     const int M = N / RADIX;
     const int W = M * K;
     const int tstride = N / (Ns * RADIX);
+    const FftIdx ix(K, Ns);
     C v[MAXB][RADIX];
     // PF: every twiddle read up front (FP32 only; worth its registers where
     // few workgroups share a CU, the column passes); otherwise the compact
@@ -327,7 +347,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
         for (int b = 0; b < MAXB; ++b) {
             const int w = tid + b * NTH;
             if (w < W) {
-                const int jm = (w / K) % Ns;
+                const int jm = ix.mod_ns(ix.row(w));
                 if constexpr (full) {
 #pragma unroll
                     for (int r = 1; r < RADIX; ++r) t[b][r - 1] = tw[jm * r * tstride];
@@ -342,7 +362,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
         for (int b = 0; b < MAXB; ++b) {
             const int w = tid + b * NTH;
             if (w < W) {
-                const int j = w / K, col = w - j * K;
+                const int j = ix.row(w), col = ix.col(w);
 #pragma unroll
                 for (int r = 0; r < RADIX; ++r) v[b][r] = load(j + r * M, col);
             }
@@ -352,9 +372,9 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
         for (int b = 0; b < MAXB; ++b) {
             const int w = tid + b * NTH;
             if (w < W) {
-                const int j = w / K, col = w - j * K;
+                const int j = ix.row(w), col = ix.col(w);
 #pragma unroll
-                for (int r = 0; r < RADIX; ++r) v[b][r] = buf[fft_lidx(j + r * M) * K + col];
+                for (int r = 0; r < RADIX; ++r) v[b][r] = buf[(fft_lidx(j + r * M) << ix.kshift) + col];
             }
         }
         if constexpr (!last) __syncthreads();
@@ -363,8 +383,8 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
     for (int b = 0; b < MAXB; ++b) {
         const int w = tid + b * NTH;
         if (w < W) {
-            const int j = w / K, col = w - j * K;
-            const int jm = j % Ns;
+            const int j = ix.row(w), col = ix.col(w);
+            const int jm = ix.mod_ns(j);
             if constexpr (!first && (full || compact)) {
                 C wr[RADIX];
                 if constexpr (full) {
@@ -389,7 +409,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int K, int Ns, const C *
                 for (int r = 0; r < RADIX; ++r) store(base + r * Ns, col, v[b][r], b * RADIX + r);
             } else {
 #pragma unroll
-                for (int r = 0; r < RADIX; ++r) buf[fft_lidx(base + r * Ns) * K + col] = v[b][r];
+                for (int r = 0; r < RADIX; ++r) buf[(fft_lidx(base + r * Ns) << ix.kshift) + col] = v[b][r];
             }
         }
     }
@@ -448,7 +468,7 @@ __device__ __forceinline__ void fft_pass_r(int r, C *buf, int N, int K, int Ns, 
     }
 }
 
-// FFT of K interleaved columns of length d.n (d.n * K <= NTH * fft_cap<NTH, CAP>()).
+// FFT of K interleaved columns of length d.n (K a power of two, d.n * K <= NTH * fft_cap<NTH, CAP>()).
 // Input: with IN_LDS the caller has written element n of column col to
 // buf[fft_lidx(n) * K + col] and synchronised; otherwise the first pass
 // calls load(n, col) -> C.  Output: with OUT_LDS the result is left at

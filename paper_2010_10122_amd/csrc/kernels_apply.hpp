@@ -915,6 +915,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
     // pixel e of the block is image row pp, column q0 + col (the float
     // quotient is exact for e < 2^20)
     const float rk = 1.0f / (float)kk;
+    const int kshift = __builtin_ctz((unsigned)K);   // K is a power of two
     auto pixel = [&](int e, int &pp, int &col) {
         pp = (int)(((float)e + 0.5f) * rk);
         col = e - pp * kk;
@@ -940,7 +941,7 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
             // image row pp sits at grid row (pp - h) mod N_u
             int ga = pp - h;
             if (ga < 0) ga += pg.nu;
-            const C hv = buf[fft_lidx(ga) * K + col];
+            const C hv = buf[(fft_lidx(ga) << kshift) + col];
             R val;
             if (pg.do_w) {
                 double ph = cj * nm1[(int64_t)pp * pg.npix_y + q0 + col];
