@@ -222,3 +222,42 @@ def test_searched_table_pinned_by_oracle():
     for s in (1.5, 2.0):
         es = [by[(a, s)][0] for a in range(4, 17) if (a, s) in by and by[(a, s)][0] > 1e-13]
         assert all(y <= x for x, y in zip(es, es[1:])), s
+
+
+def test_fft_index_quotient_is_exact():
+    """The FFT passes take j mod Ns from the FP32 reciprocal of Ns (no
+    integer division): q = trunc((j + 1/2) * fl(1/Ns)).  Exhaustively for
+    every stride Ns that a pass of any supported length can have (products
+    of the leading radices of the greedy plan, lengths up to 12288) and
+    every butterfly row j < 2^14, q equals j // Ns, in IEEE FP32 with a
+    correctly rounded reciprocal and also with the reciprocal one ulp off."""
+    def radices(n):
+        out = []
+        while n > 1:
+            for r in (16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2):
+                if n % r == 0:
+                    out.append(r)
+                    n //= r
+                    break
+            else:
+                raise AssertionError(n)
+        return out[::-1]
+    strides = set()
+    for n in range(48, 12289, 16):
+        m = n
+        for p in (2, 3, 5, 7):
+            while m % p == 0:
+                m //= p
+        if m != 1:
+            continue
+        ns = 1
+        for r in radices(n):
+            strides.add(ns)
+            ns *= r
+    j = np.arange(1 << 14, dtype=np.int64)
+    jf = j.astype(np.float32) + np.float32(0.5)
+    for ns in sorted(strides):
+        rn = np.float32(1.0) / np.float32(ns)
+        for r in (rn, np.nextafter(rn, np.float32(0)), np.nextafter(rn, np.float32(1))):
+            q = (jf * r).astype(np.float32).astype(np.int64)
+            assert np.array_equal(q, j // ns), ns
