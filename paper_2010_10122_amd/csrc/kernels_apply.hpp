@@ -921,6 +921,25 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
         col = e - pp * kk;
     };
     for (int e = threadIdx.x; e < ne; e += NTH) sum[e] = (R)0;
+    // n - 1 of this thread's pixels, read once for the batch and held in
+    // registers where they fit (kColPix a thread): a column of the n - 1
+    // table is a strided read of one 8-byte value per image row, which per
+    // plane cost more than the transform at K = 1
+    constexpr int kColPix = sizeof(R) == 4 ? 12 : 1;   // FP64: its registers are spoken for
+    const bool nm_regs = sizeof(R) == 4 && pg.do_w && ne <= NTH * kColPix;
+    double nmr[kColPix];
+    if (nm_regs) {
+#pragma unroll
+        for (int i = 0; i < kColPix; ++i) {
+            const int e = threadIdx.x + i * NTH;
+            nmr[i] = 0.0;
+            if (e < ne) {
+                int pp, col;
+                pixel(e, pp, col);
+                nmr[i] = nm1[(int64_t)pp * pg.npix_y + q0 + col];
+            }
+        }
+    }
     for (int p = 0; p < np; ++p) {
         // the K columns q0 .. lie in one panel (K divides kPanel)
         const C *src = T + p * panel_elems(pg.npix_y, pg.nu) + (int64_t)(q0 / kPanel) * pg.nu * kPanel + q0 % kPanel;
@@ -935,16 +954,15 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
                 return col < kk ? src[(int64_t)n * kPanel + col] : cmake<C>((R)0, (R)0);
             },
             NoIo{});
-        for (int e = threadIdx.x; e < ne; e += NTH) {
-            int pp, col;
-            pixel(e, pp, col);
+        // the screened real part of pixel e (n - 1 given)
+        auto screen = [&](int e, int pp, int col, double nmv) {
             // image row pp sits at grid row (pp - h) mod N_u
             int ga = pp - h;
             if (ga < 0) ga += pg.nu;
             const C hv = buf[(fft_lidx(ga) << kshift) + col];
             R val;
             if (pg.do_w) {
-                double ph = cj * nm1[(int64_t)pp * pg.npix_y + q0 + col];
+                double ph = cj * nmv;
                 ph -= rint(ph);
                 R sn, cs;
                 if constexpr (sizeof(R) == 4) sincos_turns_f32(ph, sn, cs);
@@ -954,6 +972,23 @@ __global__ __launch_bounds__(NTH) void k_cols_grid(const Cx<R> *__restrict__ T, 
                 val = hv.x;
             }
             sum[e] += val;
+        };
+        if (nm_regs) {
+#pragma unroll
+            for (int i = 0; i < kColPix; ++i) {
+                const int e = threadIdx.x + i * NTH;
+                if (e < ne) {
+                    int pp, col;
+                    pixel(e, pp, col);
+                    screen(e, pp, col, nmr[i]);
+                }
+            }
+        } else {
+            for (int e = threadIdx.x; e < ne; e += NTH) {
+                int pp, col;
+                pixel(e, pp, col);
+                screen(e, pp, col, pg.do_w ? nm1[(int64_t)pp * pg.npix_y + q0 + col] : 0.0);
+            }
         }
         __syncthreads();
     }
