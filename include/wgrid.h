@@ -128,6 +128,11 @@ int wg_plan_estimate(const wg_plan_desc *desc, size_t *plan_bytes, size_t *peak_
  *             overwritten, masked entries are set to 0
  *   workspace device scratch of at least wg_workspace_bytes(plan) bytes
  *   stream    hipStream_t (NULL = default stream); the call is asynchronous.
+ *             Its kernels run on this stream and on a second stream the plan
+ *             owns (the visibility kernels overlap the FFT passes of the
+ *             neighbouring w-batch); the second stream forks from and joins
+ *             back into this one, so the call is ordered on `stream` like a
+ *             single-stream call, also under HIP graph capture.
  * Errors: WG_EINVAL for NULL plan/dirty/vis or a short workspace; WG_EHIP. */
 int wg_degrid(const wg_plan *plan, const void *dirty, const void *wgt, void *vis,
               void *workspace, size_t workspace_bytes, void *stream);
@@ -137,7 +142,8 @@ int wg_degrid(const wg_plan *plan, const void *dirty, const void *wgt, void *vis
  *   wgt       device real [n_rows][n_chan] or NULL; multiplies the input
  *   dirty     device [npix_x][npix_y] real; fully overwritten
  * Other arguments and errors as wg_degrid.  Concurrent calls on one plan are
- * safe when each uses its own workspace and output. */
+ * safe when each uses its own workspace and output (their work on the
+ * plan's second stream runs one call after the other). */
 int wg_grid(const wg_plan *plan, const void *vis, const void *wgt, void *dirty,
             void *workspace, size_t workspace_bytes, void *stream);
 
@@ -217,7 +223,9 @@ const char *wg_strerror(int code);
  * A profiler attached to the calling host thread brackets every kernel
  * launch of wg_grid / wg_degrid with a pair of HIP events on the launch
  * stream and accumulates the elapsed time per kernel kind.  Attaching adds
- * two event records per launch; it changes no result.  A profiler is
+ * two event records per launch and runs every launch on the caller's stream
+ * (the plan's second stream is left out, so each timed kernel runs alone);
+ * it changes no result.  A profiler is
  * owned by the caller and must not be shared between host threads. */
 #define WG_KIND_GRID             0   /* LDS-tile gridder                        */
 #define WG_KIND_DEGRID           1   /* gather degridder                        */

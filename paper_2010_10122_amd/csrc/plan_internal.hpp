@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <unordered_map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/wgrid.h"
@@ -105,5 +106,12 @@ struct wg_plan {
     size_t index_bytes = 0;
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
-    size_t off_G = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
+    size_t off_G = 0, off_G2 = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
+    // the two-stream apply pipeline: a side stream for the visibility
+    // kernels and its events (created with the plan), and a lock that keeps
+    // one call's enqueue sequence whole when several host threads share the
+    // plan
+    hipStream_t side = nullptr;
+    hipEvent_t ev[6] = {};
+    mutable std::mutex enqueue_mu;
 };

@@ -405,6 +405,8 @@ size_t plan_layout(wg_plan *p, int64_t slots) {
     size_t off = 0;
     p->off_G = off;
     off = align(off + (size_t)p->P * g.nu * g.nv * sc);
+    p->off_G2 = off;                   // the second plane buffer of the pipeline
+    off = align(off + (size_t)p->P * g.nu * g.nv * sc);
     p->off_T = off;
     off = align(off + (size_t)p->P * std::max(panel_elems(g.npix_y, g.nu), panel_elems(g.nv, g.npix_x)) * sc);
     p->off_acc = off;
@@ -584,6 +586,9 @@ int plan_build(wg_plan *p) {
     const wg_plan_desc &d = p->desc;
     hipStream_t st = p->stream;
     HIP_TRY(hipGetDevice(&p->device));
+    // the apply pipeline's side stream (default priority) and events
+    HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    for (hipEvent_t &e : p->ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // set-up of the allocation-free entry point on this device (its scratch
     // address, looked up once per device); a failure is reported by that
     // entry point, not here
@@ -798,10 +803,11 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
           hipStream_t st) {
     using C = Cx<R>;
     if (!ws || ws_bytes < p->ws_bytes) return WG_EINVAL;
+    std::lock_guard<std::mutex> lock(p->enqueue_mu);
     const Geom &g = p->g;
     const wg_plan_desc &d = p->desc;
     unsigned char *w = (unsigned char *)ws;
-    C *G = (C *)(w + p->off_G);
+    C *Gbuf[2] = {(C *)(w + p->off_G), (C *)(w + p->off_G2)};
     C *T = (C *)(w + p->off_T);
     R *acc = (R *)(w + p->off_acc);
     R *itil = (R *)(w + p->off_itil);
@@ -841,21 +847,40 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 hipLaunchKernelGGL(k_gather_vis<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256),
                                    0, st, (const C *)in, (const R *)wgt, p->inv2, p->n_total, vacc);
             }
+            // Two streams (one while a profiler is attached, so that each
+            // timed launch runs alone): the gridder of batch J (side stream) fills plane
+            // buffer J mod 2 while the FFT passes of batch J - 1 (caller's
+            // stream) read the other one; the image sums stay in batch order
+            // on the caller's stream.
+            hipStream_t sd = g_prof ? st : p->side;
+            hipEvent_t e_start = p->ev[0], e_vis[2] = {p->ev[1], p->ev[2]}, e_rows[2] = {p->ev[3], p->ev[4]};
+            HIP_TRY(hipEventRecord(e_start, st));
+            HIP_TRY(hipStreamWaitEvent(sd, e_start, 0));
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
+                const int b = J & 1;
+                C *G = Gbuf[b];
+                // buffer b is free once the row pass of batch J - 2 has read it
+                if (J >= 2) HIP_TRY(hipStreamWaitEvent(sd, e_rows[b], 0));
                 {
-                    ProfScope ps(WG_KIND_GRID, st);
-                    launch_vis_kernel<R>(true, p, vg, J, G, nullptr, part, st);
+                    ProfScope ps(WG_KIND_GRID, sd);
+                    launch_vis_kernel<R>(true, p, vg, J, G, nullptr, part, sd);
                 }
-                                {
+                HIP_TRY(hipEventRecord(e_vis[b], sd));
+                HIP_TRY(hipStreamWaitEvent(st, e_vis[b], 0));
+                {
                     ProfScope ps(WG_KIND_FFT_ROWS_GRID, st);
                     DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_grid<CAP>(p, G, T, pg, np, st)));
                 }
+                HIP_TRY(hipEventRecord(e_rows[b], st));
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
                     DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
-                }            }
+                }
+            }
+            // every side-stream launch precedes the last batch's event, which
+            // the caller's stream has waited for
         }
         {
             ProfScope ps(WG_KIND_IMAGE, st);
@@ -879,21 +904,41 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 hipLaunchKernelGGL(k_fill_zero<C>, dim3((unsigned)grid_blocks(p->n_active, 256, 1 << 16)), dim3(256),
                                    0, st, vacc, p->n_active);
             }
+            // Two streams (one while a profiler is attached): the FFT passes
+            // of batch J (caller's stream) fill
+            // plane buffer J mod 2 while the degridder of batch J - 1 (side
+            // stream) reads the other one; the visibility sums stay in batch
+            // order on the side stream.
+            hipStream_t sd = g_prof ? st : p->side;
+            hipEvent_t e_start = p->ev[0], e_fft[2] = {p->ev[1], p->ev[2]}, e_vis[2] = {p->ev[3], p->ev[4]};
+            hipEvent_t e_end = p->ev[5];
+            HIP_TRY(hipEventRecord(e_start, st));
+            HIP_TRY(hipStreamWaitEvent(sd, e_start, 0));
             for (int J = 0; J < p->NJ; ++J) {
                 const int j_lo = J * p->P;
                 const int np = std::min(p->P, g.nw - j_lo);
-                                {
+                const int b = J & 1;
+                C *G = Gbuf[b];
+                {
                     ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
                     DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
                 }
+                // buffer b is free once the degridder of batch J - 2 has read it
+                if (J >= 2) HIP_TRY(hipStreamWaitEvent(st, e_vis[b], 0));
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
                     DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
-                }                {
-                    ProfScope ps(WG_KIND_DEGRID, st);
-                    launch_vis_kernel<R>(false, p, va, J, G, vacc, nullptr, st);
                 }
+                HIP_TRY(hipEventRecord(e_fft[b], st));
+                HIP_TRY(hipStreamWaitEvent(sd, e_fft[b], 0));
+                {
+                    ProfScope ps(WG_KIND_DEGRID, sd);
+                    launch_vis_kernel<R>(false, p, va, J, G, vacc, nullptr, sd);
+                }
+                HIP_TRY(hipEventRecord(e_vis[b], sd));
             }
+            HIP_TRY(hipEventRecord(e_end, sd));
+            HIP_TRY(hipStreamWaitEvent(st, e_end, 0));
             {
                 ProfScope ps(WG_KIND_VIS, st);
                 hipLaunchKernelGGL(k_degrid_finish<R>, dim3((unsigned)grid_blocks(p->n_total, 256, 1 << 16)), dim3(256),
@@ -964,6 +1009,9 @@ int wg_plan_create(const wg_plan_desc *desc, wg_plan **out) {
 
 int wg_plan_destroy(wg_plan *p) {
     if (!p) return WG_OK;
+    for (hipEvent_t &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->side) (void)hipStreamDestroy(p->side);
     p->mem.release_all();
     delete p;
     return WG_OK;
