@@ -77,6 +77,12 @@ typedef struct {
                                     planner's table, see wg_kernel_table)               */
     int            planes_per_batch; /* 0 = automatic; w-planes processed per batch,
                                         capped at alpha and at 8 (FP32) / 4 (FP64)      */
+    int            column_transform; /* 0 = automatic; 1 = one pass (K whole columns
+                                        per workgroup); 2 = four-step (N_u = n1 n2,
+                                        two passes over 16-column panels).  Automatic
+                                        takes the four-step where one pass would hold
+                                        a single column per workgroup.  Results agree
+                                        to rounding.                                  */
     void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
     wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
     wg_free_fn     free;
@@ -195,6 +201,9 @@ typedef struct {
                                  made on the grid                                    */
     double  poly_error;       /* largest |polynomial - phi| over the alpha cells of the
                                  piecewise kernel (Sect. 4.2), evaluated in FP64      */
+    int     column_transform; /* 1 = one pass, 2 = four-step (see wg_plan_desc)      */
+    int     col_n1, col_n2;   /* four-step factors of nu (0 for one pass)             */
+    int     col_k;            /* columns per workgroup of the one-pass form           */
 } wg_plan_info_t;
 
 int    wg_plan_info(const wg_plan *plan, wg_plan_info_t *info);

@@ -30,6 +30,7 @@ class PlanDesc(ctypes.Structure):
         ("alpha", ctypes.c_int),
         ("sigma", ctypes.c_double),
         ("planes_per_batch", ctypes.c_int),
+        ("column_transform", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("alloc", _alloc_fn),
         ("free", _free_fn),
@@ -72,6 +73,10 @@ class PlanInfo(ctypes.Structure):
         ("rounding_error", ctypes.c_double),
         ("amplification", ctypes.c_double),
         ("poly_error", ctypes.c_double),
+        ("column_transform", ctypes.c_int),
+        ("col_n1", ctypes.c_int),
+        ("col_n2", ctypes.c_int),
+        ("col_k", ctypes.c_int),
     ]
 
 

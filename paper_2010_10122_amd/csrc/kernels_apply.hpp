@@ -1080,6 +1080,159 @@ __global__ __launch_bounds__(NTH) void k_cols_degrid(const Cx<R> *__restrict__ T
         });
 }
 
+// ---- four-step column transform ---------------------------------------------
+// Where a whole column of length N = N_u fits a workgroup only once (one
+// column per workgroup: every global access a lone 8- or 16-byte piece of a
+// cache line), the u transform runs in two passes over the 16-column panels
+// of the intermediate, each moving whole panel rows.  With N = n1 n2,
+// input index a = n2 s + t and output index k = r + n1 q
+// (s, r < n1; t, q < n2):
+//   X[r + n1 q] = sum_t w_n2^{t q} w_N^{t r} sum_s x[n2 s + t] w_n1^{s r},
+// w_m = exp(DIR 2 pi i / m).  Pass A: for one t, the n1-point transforms
+// over s, times w_N^{t r}, into Y[p][panel][r][t][16]; pass B: for one r,
+// the n2-point transforms over t.
+struct Col4Geom {
+    int n, n1, n2;           // N = n1 n2
+    int rows_in;             // rows of the pass-A input panels
+    int h;                   // pruned input (degridding): row pp sits at a = (pp - h) mod N
+    int ncols;               // valid columns (the last panel may be partial)
+    int64_t in_plane;        // elements per plane of the input panels
+    int64_t y_plane;         // elements per plane of Y
+};
+
+// Pass A.  Block (panel * n2 + t, plane).  PRUNED: the input holds only the
+// rows_in image rows (degridding), zero elsewhere; otherwise all N rows.
+template <typename R, int NTH, int CAP, int DIR, bool PRUNED>
+__global__ __launch_bounds__(NTH) void k_col4_a(const Cx<R> *__restrict__ in, Cx<R> *__restrict__ Y,
+                                                Col4Geom cg, FftDesc fd1, const Cx<R> *__restrict__ tw1,
+                                                const Cx<R> *__restrict__ twn) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int panel = blockIdx.x / cg.n2;
+    const int t = blockIdx.x - panel * cg.n2;
+    const int p = blockIdx.y;
+    const int kk = min(kPanel, cg.ncols - panel * kPanel);
+    const C *src = in + p * cg.in_plane + (int64_t)panel * cg.rows_in * kPanel;
+    C *dst = Y + p * cg.y_plane + ((int64_t)panel * cg.n + t) * kPanel;
+    const int64_t rstride = (int64_t)cg.n2 * kPanel;
+    lds_fft<false, false, DIR, NTH, false, CAP>(
+        buf, kPanel, fd1, tw1,
+        [&](int s, int col) {
+            const int a = cg.n2 * s + t;
+            int row = a;
+            if constexpr (PRUNED) {
+                row = -1;
+                if (a < cg.rows_in - cg.h) row = a + cg.h;
+                else if (a >= cg.n - cg.h) row = a - (cg.n - cg.h);
+            }
+            return (row >= 0 && col < kk) ? src[(int64_t)row * kPanel + col] : cmake<C>((R)0, (R)0);
+        },
+        [&](int r, int col, C v, int) {
+            const C w = twn[r * t];   // exp(-2 pi i r t / N); r t < N
+            dst[(int64_t)r * rstride + col] = DIR < 0 ? cmul(v, w) : cmulconj(v, w);
+        });
+}
+
+// Pass B, degridding: block (panel * n1 + r, plane); the n2-point
+// transforms over t of Y[p][panel][r][.][.] give the grid rows a = r + n1 q of
+// the panel's columns, G[p][a][b].
+template <typename R, int NTH, int CAP>
+__global__ __launch_bounds__(NTH) void k_col4_b_degrid(const Cx<R> *__restrict__ Y, Cx<R> *__restrict__ G,
+                                                       Col4Geom cg, int nv, FftDesc fd2,
+                                                       const Cx<R> *__restrict__ tw2) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int panel = blockIdx.x / cg.n1;
+    const int r = blockIdx.x - panel * cg.n1;
+    const int p = blockIdx.y;
+    const int b0 = panel * kPanel;
+    const int kk = min(kPanel, cg.ncols - b0);
+    const C *src = Y + p * cg.y_plane + ((int64_t)panel * cg.n + (int64_t)r * cg.n2) * kPanel;
+    C *dst = G + (int64_t)p * cg.n * nv + b0;
+    lds_fft<false, false, -1, NTH, false, CAP>(
+        buf, kPanel, fd2, tw2, [&](int t, int col) { return src[t * kPanel + col]; },
+        [&](int q, int col, C v, int) {
+            if (col < kk) dst[(int64_t)(r + cg.n1 * q) * nv + col] = v;
+        });
+}
+
+// Pass B, gridding: block (panel * n1 + r) over all planes of the batch; the
+// n2-point transforms over t give grid rows a = r + n1 q; the retained ones
+// (image row pp, a = (pp - h) mod N) are multiplied by the conjugate w-screen
+// (eq. Rad1, phase reduced in FP64), their real parts summed over the planes
+// in registers and added to the image accumulator once.  Each (pp, column)
+// belongs to one block.
+template <typename R, int NTH, int CAP>
+__global__ __launch_bounds__(NTH) void k_col4_b_grid(const Cx<R> *__restrict__ Y, R *__restrict__ acc,
+                                                     const double *__restrict__ nm1, PassGeom pg, Col4Geom cg,
+                                                     int j_lo, int np, FftDesc fd2,
+                                                     const Cx<R> *__restrict__ tw2) {
+    using C = Cx<R>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int panel = blockIdx.x / cg.n1;
+    const int r = blockIdx.x - panel * cg.n1;
+    const int q0 = panel * kPanel;
+    const int kk = min(kPanel, pg.npix_y - q0);
+    const int h = pg.npix_x / 2;
+    // output e = tid + i NTH of the block: q = e / 16, column e % 16; its
+    // image pixel (flat index, -1 when not retained)
+    auto pixel = [&](int i) -> int {
+        const int e = threadIdx.x + i * NTH;
+        const int q = e >> 4, col = e & (kPanel - 1);
+        const int a = r + cg.n1 * q;
+        int pp = -1;
+        if (e < cg.n2 * kPanel && col < kk) {
+            if (a < pg.npix_x - h) pp = a + h;
+            else if (a >= cg.n - h) pp = a - (cg.n - h);
+        }
+        return pp >= 0 ? pp * pg.npix_y + q0 + col : -1;   // npix_x npix_y < 2^31
+    };
+    double nmv[CAP];
+    R sum[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        const int px = pixel(i);
+        nmv[i] = (px >= 0 && pg.do_w) ? nm1[px] : 0.0;
+        sum[i] = (R)0;
+    }
+    for (int p = 0; p < np; ++p) {
+        const C *src = Y + p * cg.y_plane + ((int64_t)panel * cg.n + (int64_t)r * cg.n2) * kPanel;
+        const double cj = pg.w0 + (double)(j_lo + p) * pg.dw;
+        // an opaque copy of the column count per plane: otherwise every FFT
+        // address is hoisted out of the plane loop and held in registers
+        int Kp = __builtin_amdgcn_readfirstlane(kPanel);
+        asm volatile("" : "+s"(Kp));
+        lds_fft<false, true, +1, NTH, false, CAP>(
+            buf, Kp, fd2, tw2, [&](int t, int col) { return src[t * kPanel + col]; }, NoIo{});
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            if (pixel(i) >= 0) {
+                const int e = threadIdx.x + i * NTH;
+                const C hv = buf[(fft_lidx(e >> 4) << 4) + (e & (kPanel - 1))];
+                if (pg.do_w) {
+                    double ph = cj * nmv[i];
+                    ph -= rint(ph);
+                    R sn, cs;
+                    if constexpr (sizeof(R) == 4) sincos_turns_f32(ph, sn, cs);
+                    else sincospi(2.0 * ph, &sn, &cs);
+                    sum[i] += hv.x * cs + hv.y * sn;   // Re(h * exp(-2 pi i ph))
+                } else {
+                    sum[i] += hv.x;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        const int px = pixel(i);
+        if (px >= 0) acc[px] += sum[i];
+    }
+}
+
 // ---- image-side elementwise kernels ----------------------------------------
 template <typename R>
 __global__ void k_scale_image(const R *__restrict__ in, const double *__restrict__ corr, R *__restrict__ out,

@@ -81,6 +81,11 @@ struct wg_plan {
     wg::FftDesc fft_u{}, fft_v{};
     int k_cols = 1;     // columns per workgroup in the strided passes
     int k_cols_d = 1;   // the same for the degridding column pass
+    // four-step column transform (N_u = n1 n2) in place of the one-pass
+    // column transforms, with its two sub-length transforms and tables
+    int col4 = 0, n1 = 0, n2 = 0;
+    wg::FftDesc fft_n1{}, fft_n2{};
+    void *tw_n1 = nullptr, *tw_n2 = nullptr;   // complex R
     // device arrays
     double *scale = nullptr;           // [n_chan]
     void *coef = nullptr;              // [degree+1][alpha] R
@@ -106,7 +111,7 @@ struct wg_plan {
     size_t index_bytes = 0;
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
-    size_t off_G = 0, off_G2 = 0, off_T = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
+    size_t off_G = 0, off_G2 = 0, off_T = 0, off_Y = 0, off_acc = 0, off_vacc = 0, off_itil = 0, off_part = 0;
     // the two-stream apply pipeline: a side stream for the visibility
     // kernels and its events (created with the plan), and a lock that keeps
     // one call's enqueue sequence whole when several host threads share the

@@ -140,6 +140,13 @@ void make_fft_desc(int n, FftDesc &d) {
     std::reverse(d.radix, d.radix + d.npass);
 }
 
+// the length a descriptor transforms (its radices' product)
+int fft_desc_len(const FftDesc &d) {
+    int n = 1;
+    for (int s = 0; s < d.npass; ++s) n *= d.radix[s];
+    return n;
+}
+
 // exp(-2 pi i t / N) with the angle folded into [0, pi/4] so that the library
 // sin/cos see a small, exactly scaled argument.
 void twiddles(int n, std::vector<double> &re, std::vector<double> &im) {
@@ -194,6 +201,20 @@ template <typename R> int build_plan_tables(wg_plan *p, const std::vector<double
     if (!p->tw_u || !p->tw_v) return WG_ENOMEM;
     HIP_TRY(hipMemcpyAsync(p->tw_u, tu.data(), tu.size() * sizeof(C), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->tw_v, tv.data(), tv.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    // four-step sub-lengths: exp(-2 pi i t / n_k) = exp(-2 pi i (t N / n_k) / N),
+    // the same values as the length-N table
+    std::vector<C> t1, t2;
+    if (p->col4) {
+        t1.resize(p->n1);
+        t2.resize(p->n2);
+        for (int t = 0; t < p->n1; ++t) t1[t] = tu[(size_t)t * p->n2];
+        for (int t = 0; t < p->n2; ++t) t2[t] = tu[(size_t)t * p->n1];
+        p->tw_n1 = p->mem.get(t1.size() * sizeof(C));
+        p->tw_n2 = p->mem.get(t2.size() * sizeof(C));
+        if (!p->tw_n1 || !p->tw_n2) return WG_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(p->tw_n1, t1.data(), t1.size() * sizeof(C), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(p->tw_n2, t2.data(), t2.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));   // the host vectors must outlive the copies
     return WG_OK;
 }
@@ -409,6 +430,9 @@ size_t plan_layout(wg_plan *p, int64_t slots) {
     off = align(off + (size_t)p->P * g.nu * g.nv * sc);
     p->off_T = off;
     off = align(off + (size_t)p->P * std::max(panel_elems(g.npix_y, g.nu), panel_elems(g.nv, g.npix_x)) * sc);
+    p->off_Y = off;                    // the four-step intermediate
+    if (p->col4)
+        off = align(off + (size_t)p->P * std::max(panel_elems(g.nv, g.nu), panel_elems(g.npix_y, g.nu)) * sc);
     p->off_acc = off;
     off = align(off + (size_t)npix * sr);
     p->off_itil = off;
@@ -438,7 +462,7 @@ void plan_footprint(const wg_plan *p, size_t &resident, size_t &peak) {
     resident = (size_t)(p->desc.n_chan * 8 + (uint64_t)(p->alpha + 4) * p->alpha * sr +
                         (uint64_t)(g.nu + g.nv) * sc +
                         2 * npix * 8 + ntot * (8 + 4 + 4 + 4) + 2 * tab_n * 4 * 5 + 2 * nact * (3 * sr + 8) +
-                        items * 16);
+                        items * 16 + (p->col4 ? (uint64_t)(p->n1 + p->n2) * sc + 512 : 0));
     // construction also holds the radix-sort scratch (second key and value
     // buffers, histograms, scan levels) and small host-table copies
     const uint64_t nblocks = (ntot + kRsTile - 1) / kRsTile;
@@ -566,6 +590,33 @@ int plan_host(wg_plan *p) {
            (int64_t)g.nu * 2 * p->k_cols <= col_values)
         p->k_cols *= 2;
     p->k_cols_d = p->k_cols;
+    // four-step column transform where the one-pass form keeps a single
+    // column per workgroup (or when asked for): N_u = n1 n2 with both
+    // factors in [17, 128] (16-column panels of n_k values fit 256 threads x
+    // 8, and each sub-length takes at least two FFT passes), as close to
+    // sqrt(N_u) as the factors allow
+    p->col4 = 0;
+    if (d.column_transform < 0 || d.column_transform > 2) return WG_EINVAL;
+    if (d.column_transform == 2 || (d.column_transform == 0 && p->k_cols == 1)) {
+        int best = 0;
+        for (int a = 17; a <= 128; ++a) {
+            if (g.nu % a != 0 || g.nu / a < 17 || g.nu / a > 128) continue;
+            FftDesc f1, f2;
+            make_fft_desc(a, f1);
+            make_fft_desc(g.nu / a, f2);
+            if (fft_desc_len(f1) != a || fft_desc_len(f2) != g.nu / a) continue;
+            if (!best || std::abs(a - g.nu / a) < std::abs(best - g.nu / best)) best = a;
+        }
+        if (best) {
+            p->col4 = 1;
+            p->n1 = best;
+            p->n2 = g.nu / best;
+            make_fft_desc(p->n1, p->fft_n1);
+            make_fft_desc(p->n2, p->fft_n2);
+        } else if (d.column_transform == 2) {
+            return WG_EUNSUPPORTED;
+        }
+    }
     // planes per batch: the gridder keeps one register accumulator per plane
     // of the batch and lane, P = alpha (a visibility's alpha planes then meet
     // at most two batches); the degridder stages P planes of tile + halo.
@@ -759,6 +810,50 @@ template <typename R, int NTH> struct FftLaunch {
     }
 };
 
+// Four-step column transform: 256 threads, 8 values a thread (16-column
+// panels of n1, n2 <= 128 values).
+template <typename R> struct Col4Launch {
+    static constexpr int NTH = 256, CAP = 8;
+    static Col4Geom geom(const wg_plan *p, bool gridding) {
+        const Geom &g = p->g;
+        Col4Geom cg;
+        cg.n = g.nu;
+        cg.n1 = p->n1;
+        cg.n2 = p->n2;
+        cg.rows_in = gridding ? g.nu : g.npix_x;
+        cg.h = gridding ? 0 : g.npix_x / 2;
+        cg.ncols = gridding ? g.npix_y : g.nv;
+        cg.in_plane = gridding ? panel_elems(g.npix_y, g.nu) : panel_elems(g.nv, g.npix_x);
+        cg.y_plane = panel_elems(cg.ncols, g.nu);
+        return cg;
+    }
+    static int panels(const Col4Geom &cg) { return (cg.ncols + kPanel - 1) / kPanel; }
+    static void pass_a(const wg_plan *p, bool gridding, const Cx<R> *in, Cx<R> *Y, int np, hipStream_t st) {
+        const Col4Geom cg = geom(p, gridding);
+        const dim3 grid(panels(cg) * cg.n2, np);
+        const size_t lds = (size_t)fft_lds_len(cg.n1) * kPanel * sizeof(Cx<R>);
+        if (gridding)
+            hipLaunchKernelGGL((k_col4_a<R, NTH, CAP, +1, false>), grid, dim3(NTH), lds, st, in, Y, cg, p->fft_n1,
+                               (const Cx<R> *)p->tw_n1, (const Cx<R> *)p->tw_u);
+        else
+            hipLaunchKernelGGL((k_col4_a<R, NTH, CAP, -1, true>), grid, dim3(NTH), lds, st, in, Y, cg, p->fft_n1,
+                               (const Cx<R> *)p->tw_n1, (const Cx<R> *)p->tw_u);
+    }
+    static void pass_b_degrid(const wg_plan *p, const Cx<R> *Y, Cx<R> *G, int np, hipStream_t st) {
+        const Col4Geom cg = geom(p, false);
+        hipLaunchKernelGGL((k_col4_b_degrid<R, NTH, CAP>), dim3(panels(cg) * cg.n1, np), dim3(NTH),
+                           (size_t)fft_lds_len(cg.n2) * kPanel * sizeof(Cx<R>), st, Y, G, cg, p->g.nv, p->fft_n2,
+                           (const Cx<R> *)p->tw_n2);
+    }
+    static void pass_b_grid(const wg_plan *p, const Cx<R> *Y, R *acc, const PassGeom &pg, int j_lo, int np,
+                            hipStream_t st) {
+        const Col4Geom cg = geom(p, true);
+        hipLaunchKernelGGL((k_col4_b_grid<R, NTH, CAP>), dim3(panels(cg) * cg.n1), dim3(NTH),
+                           (size_t)fft_lds_len(cg.n2) * kPanel * sizeof(Cx<R>), st, Y, acc, p->nm1, pg, cg, j_lo, np,
+                           p->fft_n2, (const Cx<R> *)p->tw_n2);
+    }
+};
+
 // Row transforms (K = 1, N up to the LDS limit): FP32 256/1024 threads,
 // FP64 256/512.  Column transforms: FP32 256/1024 (the wide workgroup keeps
 // 16 waves on the CU that its LDS allows), FP64 256.  Each choice keeps a
@@ -809,6 +904,7 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
     unsigned char *w = (unsigned char *)ws;
     C *Gbuf[2] = {(C *)(w + p->off_G), (C *)(w + p->off_G2)};
     C *T = (C *)(w + p->off_T);
+    C *Y = (C *)(w + p->off_Y);
     R *acc = (R *)(w + p->off_acc);
     R *itil = (R *)(w + p->off_itil);
     C *vacc = (C *)(w + p->off_vacc);
@@ -848,10 +944,10 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                                    0, st, (const C *)in, (const R *)wgt, p->inv2, p->n_total, vacc);
             }
             // Two streams (one while a profiler is attached, so that each
-            // timed launch runs alone): the gridder of batch J (side stream) fills plane
-            // buffer J mod 2 while the FFT passes of batch J - 1 (caller's
-            // stream) read the other one; the image sums stay in batch order
-            // on the caller's stream.
+            // timed launch runs alone): the gridder of batch J (side stream)
+            // fills plane buffer J mod 2 while the FFT passes of batch J - 1
+            // (caller's stream) read the other one; the image sums stay in
+            // batch order on the caller's stream.
             hipStream_t sd = g_prof ? st : p->side;
             hipEvent_t e_start = p->ev[0], e_vis[2] = {p->ev[1], p->ev[2]}, e_rows[2] = {p->ev[3], p->ev[4]};
             HIP_TRY(hipEventRecord(e_start, st));
@@ -876,7 +972,12 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                 HIP_TRY(hipEventRecord(e_rows[b], st));
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_GRID, st);
-                    DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                    if (p->col4) {
+                        Col4Launch<R>::pass_a(p, true, T, Y, np, st);
+                        Col4Launch<R>::pass_b_grid(p, Y, acc, pg, j_lo, np, st);
+                    } else {
+                        DISPATCH_COLS(g.nu * p->k_cols, (FftLaunch<R, NTH>::cols_grid(p, T, acc, pg, j_lo, np, st)));
+                    }
                 }
             }
             // every side-stream launch precedes the last batch's event, which
@@ -905,10 +1006,9 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                                    0, st, vacc, p->n_active);
             }
             // Two streams (one while a profiler is attached): the FFT passes
-            // of batch J (caller's stream) fill
-            // plane buffer J mod 2 while the degridder of batch J - 1 (side
-            // stream) reads the other one; the visibility sums stay in batch
-            // order on the side stream.
+            // of batch J (caller's stream) fill plane buffer J mod 2 while the
+            // degridder of batch J - 1 (side stream) reads the other one; the
+            // visibility sums stay in batch order on the side stream.
             hipStream_t sd = g_prof ? st : p->side;
             hipEvent_t e_start = p->ev[0], e_fft[2] = {p->ev[1], p->ev[2]}, e_vis[2] = {p->ev[3], p->ev[4]};
             hipEvent_t e_end = p->ev[5];
@@ -923,11 +1023,17 @@ int apply(const wg_plan *p, bool gridding, const void *in, const void *wgt, void
                     ProfScope ps(WG_KIND_FFT_ROWS_DEGRID, st);
                     DISPATCH_ROWS(g.nv, (FftLaunch<R, NTH>::template rows_degrid<CAP>(p, itil, T, pg, j_lo, np, st)));
                 }
-                // buffer b is free once the degridder of batch J - 2 has read it
-                if (J >= 2) HIP_TRY(hipStreamWaitEvent(st, e_vis[b], 0));
                 {
                     ProfScope ps(WG_KIND_FFT_COLS_DEGRID, st);
-                    DISPATCH_COLS_D(g.nu * p->k_cols_d, (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
+                    if (p->col4) Col4Launch<R>::pass_a(p, false, T, Y, np, st);
+                    // buffer b is free once the degridder of batch J - 2 has read it
+                    if (J >= 2) HIP_TRY(hipStreamWaitEvent(st, e_vis[b], 0));
+                    if (p->col4) {
+                        Col4Launch<R>::pass_b_degrid(p, Y, G, np, st);
+                    } else {
+                        DISPATCH_COLS_D(g.nu * p->k_cols_d,
+                                        (FftLaunch<R, NTH>::template cols_degrid<CAP>(p, T, G, pg, np, st)));
+                    }
                 }
                 HIP_TRY(hipEventRecord(e_fft[b], st));
                 HIP_TRY(hipStreamWaitEvent(sd, e_fft[b], 0));
@@ -1089,6 +1195,10 @@ int wg_plan_info(const wg_plan *p, wg_plan_info_t *info) {
     info->rounding_error = p->round_err;
     info->amplification = p->amp;
     info->poly_error = p->poly_err;
+    info->column_transform = p->col4 ? 2 : 1;
+    info->col_n1 = p->col4 ? p->n1 : 0;
+    info->col_n2 = p->col4 ? p->n2 : 0;
+    info->col_k = p->k_cols;
     return WG_OK;
 }
 

@@ -19,6 +19,10 @@ _DTYPES = {
 }
 
 
+# column transform of the u axis: planner's choice, one pass, four-step
+_COLUMN_TRANSFORMS = {None: 0, "auto": 0, "one-pass": 1, "four-step": 2}
+
+
 def _precision_of(p):
     if p in (_lib.WG_F32, "f32", "float32", torch.float32, torch.complex64, np.float32, np.complex64):
         return _lib.WG_F32
@@ -63,7 +67,7 @@ class _TorchAllocator:
 
 
 def _fill_desc(d, uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision, do_wgridding,
-               alpha, sigma, planes_per_batch, stream, allocator):
+               alpha, sigma, planes_per_batch, stream, allocator, column_transform=None):
     d.uvw = uvw.data_ptr()
     d.freq = freq.data_ptr()
     d.mask = mask.data_ptr() if mask is not None else None
@@ -79,6 +83,7 @@ def _fill_desc(d, uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon
     d.alpha = int(alpha or 0)
     d.sigma = float(sigma or 0.0)
     d.planes_per_batch = int(planes_per_batch or 0)
+    d.column_transform = _COLUMN_TRANSFORMS[column_transform]
     d.stream = _stream_handle(stream).value
     if allocator is not None:
         d.alloc = allocator.c_alloc
@@ -95,11 +100,13 @@ class Plan:
     precision: "f32" (epsilon >= 1e-5) or "f64".
     alpha/sigma force a kernel of the planner's table (wg_kernel_table);
     planes_per_batch forces the w-plane batch size.
+    column_transform: None/"auto", "one-pass" or "four-step" (u transform
+    form; results agree to rounding).
     """
 
     def __init__(self, uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision="f32",
                  do_wgridding=True, mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None,
-                 torch_allocator=True):
+                 torch_allocator=True, column_transform=None):
         lib = _lib.load()
         for name, t, dt in (("uvw", uvw, torch.float64), ("freq", freq, torch.float64)):
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
@@ -122,7 +129,8 @@ class Plan:
         # (torch_allocator=False: hipMalloc / hipFree inside the library)
         self._alloc = _TorchAllocator(self.device, stream) if torch_allocator else None
         d = _fill_desc(_lib.PlanDesc(), uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon,
-                       self.precision, do_wgridding, alpha, sigma, planes_per_batch, stream, self._alloc)
+                       self.precision, do_wgridding, alpha, sigma, planes_per_batch, stream, self._alloc,
+                       column_transform)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             rc = lib.wg_plan_create(ctypes.byref(d), ctypes.byref(handle))
@@ -139,7 +147,7 @@ class Plan:
 
     @staticmethod
     def estimate(uvw, freq, npix_x, npix_y, pixsize_x, pixsize_y, epsilon, precision="f32", do_wgridding=True,
-                 mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None):
+                 mask=None, alpha=None, sigma=None, planes_per_batch=None, stream=None, column_transform=None):
         """Device bytes (plan, peak during construction, workspace bound) of the
         plan these arguments would build, without building it
         (``wg_plan_estimate``)."""
@@ -149,7 +157,8 @@ class Plan:
             stream = torch.cuda.current_stream(dev)
         alloc = _TorchAllocator(dev, stream)
         d = _fill_desc(_lib.PlanDesc(), uvw, freq, mask, npix_x, npix_y, pixsize_x, pixsize_y, epsilon,
-                       _precision_of(precision), do_wgridding, alpha, sigma, planes_per_batch, stream, alloc)
+                       _precision_of(precision), do_wgridding, alpha, sigma, planes_per_batch, stream, alloc,
+                       column_transform)
         pb, pk, wb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         with torch.cuda.device(dev):
             rc = lib.wg_plan_estimate(ctypes.byref(d), ctypes.byref(pb), ctypes.byref(pk), ctypes.byref(wb))

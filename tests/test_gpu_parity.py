@@ -336,13 +336,15 @@ def test_grid_stream_order(dev, which):
         res["plan"].close()
 
 
+@pytest.mark.parametrize("column_transform", ["auto", "one-pass"])
 @pytest.mark.parametrize("npix,sigma,prec", [(3584, 1.8, "f32"), (4096, 1.6, "f32"), (3584, 1.9, "f32"),
                                              (4096, 1.5, "f64")])
-def test_large_fft_lengths_vs_direct(dev, npix, sigma, prec):
+def test_large_fft_lengths_vs_direct(dev, npix, sigma, prec, column_transform):
     """Grid lengths just above 6144 (6480, 6720, 6912 FP32; 6144 FP64): the
-    column passes' block width must keep N K within what one workgroup's
-    transform holds.  A few point sources and 16,000 visibilities, both
-    directions against the direct sum on samples."""
+    one-pass column transform must keep N K within what one workgroup's
+    transform holds, and the planner takes the four-step form here (one
+    column per workgroup otherwise).  A few point sources and 16,000
+    visibilities, both directions against the direct sum on samples."""
     import paper_2010_10122_amd as wg
     rng = np.random.default_rng(npix + int(100 * sigma))
     c = synth.meerkat_like(n_dumps=4, n_chan=8, with_mask=False)
@@ -350,9 +352,11 @@ def test_large_fft_lengths_vs_direct(dev, npix, sigma, prec):
     pix = 1.6 * math.pi / 180 / 4096
     eps = 1e-4
     plan = wg.Plan(torch.from_numpy(uvw_h).to(dev), torch.from_numpy(freq_h).to(dev), npix, npix, pix, pix, eps,
-                   prec, alpha=7, sigma=sigma)
+                   prec, alpha=7, sigma=sigma, column_transform=column_transform)
     info = plan.info
-    print(f"[long fft] {prec} N={info['nu']} Nw={info['nw']}", flush=True)
+    print(f"[long fft] {prec} N={info['nu']} Nw={info['nw']} columns={info['column_transform']} "
+          f"({info['col_n1']} x {info['col_n2']}, K={info['col_k']})", flush=True)
+    assert info["column_transform"] == (2 if column_transform == "auto" else 1)
     rdt = plan.real_dtype
     dirty = np.zeros((npix, npix))
     dirty[rng.integers(0, npix, 12), rng.integers(0, npix, 12)] = rng.random(12) + 0.5
@@ -369,3 +373,43 @@ def test_large_fft_lengths_vs_direct(dev, npix, sigma, prec):
     assert np.isfinite(vis).all() and np.isfinite(img).all()
     assert e_deg < eps and e_grid < eps
     plan.close()
+
+
+@pytest.mark.parametrize("prec,alpha,sigma", [("f64", 10, 1.8), ("f32", 7, 1.8)])
+def test_four_step_columns_same_plan_as_o2(dev, prec, alpha, sigma):
+    """The four-step u transform (N_u = n1 n2, two passes over 16-column
+    panels) against O2 at the same plan in both directions, and against the
+    one-pass form of the same plan.  The 264 x 232 image gives N_u = 480 =
+    20 x 24 and a partial last panel (232 columns = 14.5 panels); four
+    channels and an earth-rotation track give several w-batches."""
+    rng = np.random.default_rng(41)
+    ant = synth.antennas_disk(rng, 12, 3000.0)
+    uvw = synth.earth_rotation_uvw(ant, 6.0, 8)[:500]
+    freq = synth.channels(0.9e9, 1.7e9, 4)
+    pix = 6.0 * math.pi / 180 / 264
+    case = dict(uvw=uvw, freq=freq, npix_x=264, npix_y=232, pixsize_x=pix, pixsize_y=pix,
+                vis=synth.complex_gaussian(rng, (uvw.shape[0], len(freq))), dirty=rng.standard_normal((264, 232)))
+    out = {}
+    for ct in ("four-step", "one-pass"):
+        res = run_product(case, 1e-2, prec, torch, dev, dirty=case["dirty"], vis=case["vis"], alpha=alpha,
+                          sigma=sigma, column_transform=ct)
+        info = res["info"]
+        assert info["column_transform"] == (2 if ct == "four-step" else 1)
+        out[ct] = res
+    info = out["four-step"]["info"]
+    assert (info["nu"], info["col_n1"] * info["col_n2"]) == (480, 480)
+    assert info["nw"] > 2 * info["planes_per_batch"]
+    pl = oracle_plan_from(info, case)
+    d2 = o2.degrid(case["uvw"], case["freq"], case["dirty"], pl)
+    i2 = o2.grid(case["uvw"], case["freq"], case["vis"], pl)
+    tol = max(pl["eps_k"], 2.0 * info["rounding_error"], 1e-13)
+    r4, r1 = out["four-step"], out["one-pass"]
+    ev, ei = rel(r4["vis"], d2), rel(r4["img"], i2)
+    dv, di = rel(r4["vis"], r1["vis"]), rel(r4["img"], r1["img"])
+    print(f"[four-step] {prec} {info['col_n1']}x{info['col_n2']} Nw={info['nw']}: vs O2 degrid {ev:.2e} "
+          f"grid {ei:.2e} (tol {tol:.2e}); vs one pass {dv:.2e} {di:.2e}", flush=True)
+    assert ev < tol and ei < tol
+    # both forms differ by the order of the FFT's roundings only
+    assert dv < 2.0 * info["rounding_error"] and di < 2.0 * info["rounding_error"]
+    for r in out.values():
+        r["plan"].close()
