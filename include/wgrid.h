@@ -81,8 +81,8 @@ typedef struct {
                                         per workgroup); 2 = four-step (N_u = n1 n2,
                                         two passes over 16-column panels).  Automatic
                                         takes the four-step where one pass would hold
-                                        a single column per workgroup.  Results agree
-                                        to rounding.                                  */
+                                        at most two columns per workgroup.  Results
+                                        agree to rounding.                            */
     void          *stream;       /* hipStream_t used for plan construction (NULL = 0)   */
     wg_alloc_fn    alloc;        /* optional device allocator (both or neither)         */
     wg_free_fn     free;

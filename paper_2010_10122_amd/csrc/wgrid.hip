@@ -590,14 +590,16 @@ int plan_host(wg_plan *p) {
            (int64_t)g.nu * 2 * p->k_cols <= col_values)
         p->k_cols *= 2;
     p->k_cols_d = p->k_cols;
-    // four-step column transform where the one-pass form keeps a single
-    // column per workgroup (or when asked for): N_u = n1 n2 with both
+    // four-step column transform where the one-pass form keeps at most two
+    // columns per workgroup (its row pieces are then 16 or 32 bytes; at four
+    // FP32 columns the one-pass form measured faster), or when asked for:
+    // N_u = n1 n2 with both
     // factors in [17, 128] (16-column panels of n_k values fit 256 threads x
     // 8, and each sub-length takes at least two FFT passes), as close to
     // sqrt(N_u) as the factors allow
     p->col4 = 0;
     if (d.column_transform < 0 || d.column_transform > 2) return WG_EINVAL;
-    if (d.column_transform == 2 || (d.column_transform == 0 && p->k_cols == 1)) {
+    if (d.column_transform == 2 || (d.column_transform == 0 && p->k_cols <= 2)) {
         int best = 0;
         for (int a = 17; a <= 128; ++a) {
             if (g.nu % a != 0 || g.nu / a < 17 || g.nu / a > 128) continue;
