@@ -436,8 +436,8 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 //     D[n][m] += sum_k  dk_k[n] * (ku_k[row m] kv_k[col m]),
 // where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility (its
 // real or imaginary part) times its w weight on plane slot n / 2; phase 1
-// stores the value and the rotated w weights, a lane forms its dk with one
-// product.  That is one v_mfma_f32_16x16x4_f32: lane l supplies
+// stores the 16 values dk[n] of each visibility, so that a lane reads its
+// operand with one LDS read.  That is one v_mfma_f32_16x16x4_f32: lane l supplies
 // A[n = l % 16][k] = dk and B[k][m = l % 16] = the uv weight of the cell,
 // k = l / 16, and ends holding D[4 (l / 16) + i][l % 16], i.e. cell l % 16
 // of planes 2 (l / 16) and 2 (l / 16) + 1.  The u and v kernel rows sit
@@ -462,13 +462,13 @@ template <int ALPHA> struct GridStageMx1 {
     static constexpr int S = CH + 1;
     static constexpr int KP = ALPHA + 3;
     static constexpr int NKP = (S + 1) * KP + 16;
-    static constexpr int NW = 8;
+    static constexpr int NW = 8;                   // plane slots
+    static constexpr int ND = 2 * NW;              // A-operand values of a slot (re, im per plane slot)
     static constexpr int LST = CH + 8;             // per-region list: entries + padding
     static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
     static constexpr size_t off_kv = al((size_t)NKP * sizeof(float));
-    static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(float));
-    static constexpr size_t off_d = al(off_kw + (size_t)S * NW * sizeof(float));
-    static constexpr size_t off_bs = al(off_d + (size_t)S * sizeof(float2));
+    static constexpr size_t off_dk = al(off_kv + (size_t)NKP * sizeof(float));
+    static constexpr size_t off_bs = al(off_dk + (size_t)S * ND * sizeof(float));
     static constexpr size_t off_list = al(off_bs + (size_t)S * sizeof(int2));
     static constexpr size_t off_coef = al(off_list + (size_t)16 * LST);
     static constexpr size_t bytes = off_coef + kCoefBytes<float, ALPHA>;
@@ -479,13 +479,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
                 float2 *__restrict__ G, float2 *__restrict__ part) {
     using ST = GridStageMx1<ALPHA>;
-    constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW, LST = ST::LST;
+    constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW, ND = ST::ND, LST = ST::LST;
     static_assert(PS <= NW, "one w weight per plane slot");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *s_ku = reinterpret_cast<float *>(smem_raw);
     float *s_kv = reinterpret_cast<float *>(smem_raw + ST::off_kv);
-    float *s_kw = reinterpret_cast<float *>(smem_raw + ST::off_kw);
-    float *s_d = reinterpret_cast<float *>(smem_raw + ST::off_d);
+    float *s_dk = reinterpret_cast<float *>(smem_raw + ST::off_dk);
     int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);
     uint8_t *s_list = reinterpret_cast<uint8_t *>(smem_raw + ST::off_list);
     float *s_coef = reinterpret_cast<float *>(smem_raw + ST::off_coef);
@@ -524,8 +523,7 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
         s_ku[e] = 0.f;
         s_kv[e] = 0.f;
     }
-    if (lane < NW) s_kw[CH * NW + lane] = 0.f;
-    if (lane < 2) s_d[CH * 2 + lane] = 0.f;
+    if (lane < ND) s_dk[CH * ND + lane] = 0.f;
     if (lane == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
     for (int e = lane; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
     f32x4 acc[16];
@@ -557,15 +555,17 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
 #pragma unroll
                 for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? 1.f : 0.f;
             }
-            float4 *pw = reinterpret_cast<float4 *>(s_kw + lane * NW);
+            // the A operand of this slot, once: value n = 2 r + (re, im) is
+            // the visibility's real or imaginary part times the w weight of
+            // plane slot r (zero past the batch's slots)
+            float4 *pd = reinterpret_cast<float4 *>(s_dk + lane * ND);
 #pragma unroll
-            for (int n = 0; n < NW / 4; ++n) {
-                const int r0 = 4 * n;
-                pw[n] = make_float4(r0 < PS ? ws[r0 < PS ? r0 : 0] : 0.f, r0 + 1 < PS ? ws[r0 + 1 < PS ? r0 + 1 : 0] : 0.f,
-                                    r0 + 2 < PS ? ws[r0 + 2 < PS ? r0 + 2 : 0] : 0.f,
-                                    r0 + 3 < PS ? ws[r0 + 3 < PS ? r0 + 3 : 0] : 0.f);
+            for (int n4 = 0; n4 < ND / 4; ++n4) {
+                const int r0 = 2 * n4, r1 = 2 * n4 + 1;
+                const float w0 = r0 < PS ? ws[r0 < PS ? r0 : 0] : 0.f;
+                const float w1 = r1 < PS ? ws[r1 < PS ? r1 : 0] : 0.f;
+                pd[n4] = make_float4(in.d.x * w0, in.d.y * w0, in.d.x * w1, in.d.y * w1);
             }
-            reinterpret_cast<float2 *>(s_d)[lane] = in.d;
         }
         // region lists from the wave's ballots: region rg holds, in lane
         // order, the slots whose footprint meets it, padded with the zero
@@ -611,8 +611,7 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
             for (int j = 0; j < n4; j += 4) {
                 const float kua = s_ku[bsa.x + rowa], kva = s_kv[bsa.y + cola];
                 const float kub = s_ku[bsb.x + rowb], kvb = s_kv[bsb.y + colb];
-                const float ava = s_d[2 * va + (m & 1)] * s_kw[va * NW + (m >> 1)];
-                const float avb = s_d[2 * vb + (m & 1)] * s_kw[vb * NW + (m >> 1)];
+                const float ava = s_dk[va * ND + m], avb = s_dk[vb * ND + m];
                 unsigned vna = lsta[min(j + 4, n4a)], vnb = lstb[min(j + 4, n4b)];
                 int2 bsna = s_bs[vna], bsnb = s_bs[vnb];
                 acc[qa] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, kua * kva, acc[qa], 0, 0, 0);
