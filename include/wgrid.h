@@ -76,7 +76,7 @@ typedef struct {
     double         sigma;        /* 0 = automatic; else force oversampling (a row of the
                                     planner's table, see wg_kernel_table)               */
     int            planes_per_batch; /* 0 = automatic; w-planes processed per batch,
-                                        capped at alpha and at 8 (FP32) / 4 (FP64)      */
+                                        capped at alpha and at 8                        */
     int            column_transform; /* 0 = automatic; 1 = one pass (K whole columns
                                         per workgroup); 2 = four-step (N_u = n1 n2,
                                         two passes over 16-column panels).  Automatic

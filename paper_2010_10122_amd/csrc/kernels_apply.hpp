@@ -446,6 +446,18 @@ __global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *_
 // indexes a kernel value or a zero.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R> using MfmaAcc = std::conditional_t<sizeof(R) == 4, f32x4, f64x4>;
+// D += A B for one 16x16x4 product (FP32 or FP64 matrix cores); lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds 4 values of
+// column l % 16 of D: rows 4 (l / 16) + i (FP32) or 4 i + l / 16 (FP64),
+// i = 0 .. 3.
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma_16x16x4(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Gridder, FP32 on the matrix cores (adjoint, eqs. Rad2 / R2 bracket).
 // One 64-lane workgroup per work item (a tile and batch, or a share of a
@@ -456,8 +468,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // masks) into LDS; region lists from the wave's ballots; phase 2 one
 // v_mfma_f32_16x16x4_f32 per region and four listed visibilities, two
 // regions at a time (see the design notes for the operand layout).  168
-// registers: three waves a SIMD (four would spill).
-template <int ALPHA> struct GridStageMx1 {
+// registers: three waves a SIMD (four would spill).  FP64 takes the same
+// form with v_mfma_f64_16x16x4_f64 (its D holds the same 16 x 16 layout,
+// four values a lane), twice the accumulator registers: two waves a SIMD.
+template <typename R, int ALPHA> struct GridStageMx1 {
     static constexpr int CH = 64;
     static constexpr int S = CH + 1;
     static constexpr int KP = ALPHA + 3;
@@ -466,28 +480,29 @@ template <int ALPHA> struct GridStageMx1 {
     static constexpr int ND = 2 * NW;              // A-operand values of a slot (re, im per plane slot)
     static constexpr int LST = CH + 8;             // per-region list: entries + padding
     static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
-    static constexpr size_t off_kv = al((size_t)NKP * sizeof(float));
-    static constexpr size_t off_dk = al(off_kv + (size_t)NKP * sizeof(float));
-    static constexpr size_t off_bs = al(off_dk + (size_t)S * ND * sizeof(float));
+    static constexpr size_t off_kv = al((size_t)NKP * sizeof(R));
+    static constexpr size_t off_dk = al(off_kv + (size_t)NKP * sizeof(R));
+    static constexpr size_t off_bs = al(off_dk + (size_t)S * ND * sizeof(R));
     static constexpr size_t off_list = al(off_bs + (size_t)S * sizeof(int2));
     static constexpr size_t off_coef = al(off_list + (size_t)16 * LST);
-    static constexpr size_t bytes = off_coef + kCoefBytes<float, ALPHA>;
+    static constexpr size_t bytes = off_coef + kCoefBytes<R, ALPHA>;
 };
 
-template <int ALPHA, int PS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
-                float2 *__restrict__ G, float2 *__restrict__ part) {
-    using ST = GridStageMx1<ALPHA>;
+template <typename R, int ALPHA, int PS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+void k_grid_mx1(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra, int cap,
+                Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
+    using C = Cx<R>;
+    using ST = GridStageMx1<R, ALPHA>;
     constexpr int CH = ST::CH, KP = ST::KP, NW = ST::NW, ND = ST::ND, LST = ST::LST;
     static_assert(PS <= NW, "one w weight per plane slot");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *s_ku = reinterpret_cast<float *>(smem_raw);
-    float *s_kv = reinterpret_cast<float *>(smem_raw + ST::off_kv);
-    float *s_dk = reinterpret_cast<float *>(smem_raw + ST::off_dk);
+    R *s_ku = reinterpret_cast<R *>(smem_raw);
+    R *s_kv = reinterpret_cast<R *>(smem_raw + ST::off_kv);
+    R *s_dk = reinterpret_cast<R *>(smem_raw + ST::off_dk);
     int2 *s_bs = reinterpret_cast<int2 *>(smem_raw + ST::off_bs);
     uint8_t *s_list = reinterpret_cast<uint8_t *>(smem_raw + ST::off_list);
-    float *s_coef = reinterpret_cast<float *>(smem_raw + ST::off_coef);
+    R *s_coef = reinterpret_cast<R *>(smem_raw + ST::off_coef);
 
     const Geom &g = a.g;
     int4 item;
@@ -504,8 +519,8 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
     const uint32_t last = min(tb.total, first + (uint32_t)item.z);
     struct In {
         int2 an;
-        float2 d;
-        float zu, zv, zw;
+        C d;
+        R zu, zv, zw;
     };
     auto load_in = [&](uint32_t pos) {
         In r;
@@ -520,15 +535,15 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
     In in{};
     if (first + lane < last) in = load_in(first + lane);
     for (int e = lane; e < ST::NKP; e += CH) {
-        s_ku[e] = 0.f;
-        s_kv[e] = 0.f;
+        s_ku[e] = (R)0;
+        s_kv[e] = (R)0;
     }
-    if (lane < ND) s_dk[CH * ND + lane] = 0.f;
+    if (lane < ND) s_dk[CH * ND + lane] = (R)0;
     if (lane == 0) s_bs[CH] = make_int2(CH * KP, CH * KP);
     for (int e = lane; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
-    f32x4 acc[16];
+    MfmaAcc<R> acc[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 16; ++q) acc[q] = MfmaAcc<R>{(R)0, (R)0, (R)0, (R)0};
     __syncthreads();
 
     for (uint32_t base = first; base < last; base += CH) {
@@ -539,32 +554,43 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
             int la0, lb0;
             footprint_masks<ALPHA>(in.an, A, B, g, la0, lb0, bm, cm);
             s_bs[lane] = make_int2(3 + lane * KP - la0, 3 + lane * KP - lb0);
-            float ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, float>(g.do_w, in.zu, in.zv, in.zw, s_coef, a.degree, ku, kv, kw);
-            float *pu = s_ku + 3 + lane * KP;
-            float *pv = s_kv + 3 + lane * KP;
+            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
+            kernel_values_z3<ALPHA, R>(g.do_w, in.zu, in.zv, in.zw, s_coef, a.degree, ku, kv, kw);
+            R *pu = s_ku + 3 + lane * KP;
+            R *pv = s_kv + 3 + lane * KP;
 #pragma unroll
             for (int i = 0; i < ALPHA; ++i) {
                 pu[i] = ku[i];
                 pv[i] = kv[i];
             }
-            float ws[PS];
+            R ws[PS];
             if (g.do_w) {
-                rotate_w<float, ALPHA, PS>(kw, j_lo - iw, ws);
+                rotate_w<R, ALPHA, PS>(kw, j_lo - iw, ws);
             } else {
 #pragma unroll
-                for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? 1.f : 0.f;
+                for (int rr = 0; rr < PS; ++rr) ws[rr] = rr == 0 ? (R)1 : (R)0;
             }
-            // the A operand of this slot, once: value n = 2 r + (re, im) is
-            // the visibility's real or imaginary part times the w weight of
-            // plane slot r (zero past the batch's slots)
-            float4 *pd = reinterpret_cast<float4 *>(s_dk + lane * ND);
+            // the A operand of this slot, once: row n holds the visibility's
+            // real or imaginary part times the w weight of a plane slot r
+            // (zero past the batch's slots), so that lane l ends with slots
+            // 2 (l / 16) and 2 (l / 16) + 1 as (re, im) pairs: n = 2 r + c
+            // with the FP32 result layout, n = 4 (2 (r % 2) + c) + r / 2
+            // with the FP64 one
+            if constexpr (sizeof(R) == 4) {
+                C *pd = reinterpret_cast<C *>(s_dk + lane * ND);
 #pragma unroll
-            for (int n4 = 0; n4 < ND / 4; ++n4) {
-                const int r0 = 2 * n4, r1 = 2 * n4 + 1;
-                const float w0 = r0 < PS ? ws[r0 < PS ? r0 : 0] : 0.f;
-                const float w1 = r1 < PS ? ws[r1 < PS ? r1 : 0] : 0.f;
-                pd[n4] = make_float4(in.d.x * w0, in.d.y * w0, in.d.x * w1, in.d.y * w1);
+                for (int r = 0; r < NW; ++r) {
+                    const R wr = r < PS ? ws[r < PS ? r : 0] : (R)0;
+                    pd[r] = cmake<C>(in.d.x * wr, in.d.y * wr);
+                }
+            } else {
+                R *pd = s_dk + lane * ND;
+#pragma unroll
+                for (int r = 0; r < NW; ++r) {
+                    const R wr = r < PS ? ws[r < PS ? r : 0] : (R)0;
+                    pd[4 * (2 * (r % 2)) + r / 2] = in.d.x * wr;
+                    pd[4 * (2 * (r % 2) + 1) + r / 2] = in.d.y * wr;
+                }
             }
         }
         // region lists from the wave's ballots: region rg holds, in lane
@@ -609,13 +635,13 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
             unsigned va = lsta[0], vb = lstb[0];
             int2 bsa = s_bs[va], bsb = s_bs[vb];
             for (int j = 0; j < n4; j += 4) {
-                const float kua = s_ku[bsa.x + rowa], kva = s_kv[bsa.y + cola];
-                const float kub = s_ku[bsb.x + rowb], kvb = s_kv[bsb.y + colb];
-                const float ava = s_dk[va * ND + m], avb = s_dk[vb * ND + m];
+                const R kua = s_ku[bsa.x + rowa], kva = s_kv[bsa.y + cola];
+                const R kub = s_ku[bsb.x + rowb], kvb = s_kv[bsb.y + colb];
+                const R ava = s_dk[va * ND + m], avb = s_dk[vb * ND + m];
                 unsigned vna = lsta[min(j + 4, n4a)], vnb = lstb[min(j + 4, n4b)];
                 int2 bsna = s_bs[vna], bsnb = s_bs[vnb];
-                acc[qa] = __builtin_amdgcn_mfma_f32_16x16x4f32(ava, kua * kva, acc[qa], 0, 0, 0);
-                acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avb, kub * kvb, acc[qb], 0, 0, 0);
+                acc[qa] = mfma_16x16x4(ava, kua * kva, acc[qa]);
+                acc[qb] = mfma_16x16x4(avb, kub * kvb, acc[qb]);
                 asm volatile("" : "+v"(vna), "+v"(bsna.x), "+v"(bsna.y), "+v"(vnb), "+v"(bsnb.x), "+v"(bsnb.y));
                 va = vna;
                 bsa = bsna;
@@ -630,7 +656,7 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int row = 4 * (q >> 2) + mr, colw = 4 * (q & 3) + cc;
-        float2 *dst;
+        C *dst;
         int64_t pstride;
         if (item.w < 0) {
             dst = G + (int64_t)(A * kTileCells + row) * g.nv + (B * kTileCells + colw);
@@ -639,8 +665,8 @@ void k_grid_mx1(VisArgs<float> a, int J, const int4 *__restrict__ extra, int n_e
             dst = part + (size_t)item.w * a.P * kTileArea + row * kTileCells + colw;
             pstride = kTileArea;
         }
-        if (r0 < np) dst[r0 * pstride] = make_float2(acc[q][0], acc[q][1]);
-        if (r0 + 1 < np) dst[(r0 + 1) * pstride] = make_float2(acc[q][2], acc[q][3]);
+        if (r0 < np) dst[r0 * pstride] = cmake<C>(acc[q][0], acc[q][1]);
+        if (r0 + 1 < np) dst[(r0 + 1) * pstride] = cmake<C>(acc[q][2], acc[q][3]);
     }
 }
 

@@ -26,26 +26,21 @@ template <typename R, int ALPHA> struct Launch {
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     template <int PS>
-    static void grid_mx(const wg_plan *p, const VisArgs<float> &va, int J, float2 *G, float2 *part,
-                        hipStream_t st) {
+    static void grid_mx(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
         const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
-        const size_t lds = GridStageMx1<ALPHA>::bytes;
-        hipLaunchKernelGGL((k_grid_mx1<ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(64), lds, st, va, J,
+        const size_t lds = GridStageMx1<R, ALPHA>::bytes;
+        hipLaunchKernelGGL((k_grid_mx1<R, ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(64), lds, st, va, J,
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        if constexpr (sizeof(R) == 4) {      // FP32: matrix cores, except for a single plane (no w
-            if (p->P == 1)                   // term), where 14 of their 16 plane-value rows would be idle
-                grid_ps<1>(p, va, J, G, part, st);
-            else if (p->P > 4)
-                grid_mx<8>(p, va, J, G, part, st);
-            else
-                grid_mx<4>(p, va, J, G, part, st);
-        } else if (p->P == 1) {              // one plane (no w term): one accumulator slot
+        // matrix cores (FP32 and FP64), except for a single plane (no w
+        // term), where 14 of their 16 plane-value rows would be idle
+        if (p->P == 1)
             grid_ps<1>(p, va, J, G, part, st);
-        } else {
-            grid_ps<4>(p, va, J, G, part, st);
-        }
+        else if (p->P > 4)
+            grid_mx<8>(p, va, J, G, part, st);
+        else
+            grid_mx<4>(p, va, J, G, part, st);
         // partial tiles of split items, added in item order
         const uint32_t nr = p->xr_off[J + 1] - p->xr_off[J];
         if (nr > 0) {

@@ -619,12 +619,11 @@ int plan_host(wg_plan *p) {
             return WG_EUNSUPPORTED;
         }
     }
-    // planes per batch: the gridder keeps one register accumulator per plane
-    // of the batch and lane, P = alpha (a visibility's alpha planes then meet
-    // at most two batches); the degridder stages P planes of tile + halo.
-    // planes per batch: at most alpha, and at most the gridder's register
-    // plane slots (8 in FP32, 4 in FP64)
-    const int max_slots = d.precision == WG_F32 ? 8 : 4;
+    // planes per batch: P = alpha (a visibility's alpha planes then meet at
+    // most two batches), at most the 8 plane slots of the matrix-core
+    // gridders (the 16 rows of their 16 x 16 products, re and im per slot);
+    // the degridder stages the batch's planes a group at a time
+    const int max_slots = 8;
     p->P = d.planes_per_batch > 0 ? std::min(d.planes_per_batch, p->alpha) : p->alpha;
     p->P = std::min(std::min(p->P, max_slots), g.nw);
     p->NJ = (g.nw + p->P - 1) / p->P;
