@@ -33,9 +33,11 @@ template <typename R, int ALPHA> struct Launch {
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        // matrix cores (FP32 and FP64), except for a single plane (no w
-        // term), where 14 of their 16 plane-value rows would be idle
-        if (p->P == 1)
+        // matrix cores, except for FP32 plans of a single plane (no w term),
+        // where 14 of their 16 plane-value rows would be idle; in FP64 the
+        // matrix-core form stays faster even then (Sect. 6.2 shape: 339
+        // against 462 ms a call)
+        if (p->P == 1 && sizeof(R) == 4)
             grid_ps<1>(p, va, J, G, part, st);
         else if (p->P > 4)
             grid_mx<8>(p, va, J, G, part, st);
