@@ -34,7 +34,7 @@ template <typename R> struct VisArgs {
 
 // ---------------------------------------------------------------------------
 // Gridder (adjoint, eq. Rad2 before the FFT).  One workgroup owns one 16x16
-// tile of the grid for the (at most PS) planes of batch J and accumulates
+// tile of the grid for the (at most 8) planes of batch J and accumulates
 // every visibility whose kernel footprint reaches the tile: those anchored in
 // the tile itself and in the three neighbouring tiles up/left (a footprint
 // spans at most alpha <= 16 cells).  No two workgroups write the same grid
@@ -46,50 +46,12 @@ template <typename R> struct VisArgs {
 // whose list is longer is split over several items: the first writes the
 // grid planes, the others write partial tiles to scratch, and k_grid_reduce
 // adds those to the planes in item order, so the sum order is fixed.
-//
-// Visibilities are taken in chunks of CH.  Phase 1, one thread per
-// visibility: tile-relative anchor, weighted value, the u and v kernel values
-// (zero-padded by three cells on each side, so that any cell of a 4x4 region
-// the footprint meets indexes inside the padded row) and the w weights
-// rotated onto the batch's plane slots go to LDS, plus a 16-bit mask of the
-// 4x4 regions of the tile the footprint meets; per-region lists are built
-// with wave ballots.  Phase 2: wave w owns the four regions of rows
-// 4w..4w+3; its lanes form four groups of 16, one cell of the region each,
-// and the groups take four different visibilities of the region's list at a
-// time (so a footprint of alpha^2 cells keeps most lanes busy), each lane
-// holding its cell's PS plane accumulators for the four regions in
-// registers.  At the flush the four groups' partial sums are added with
-// cross-lane shuffles.  Every LDS access in phase 2 is a read, so waves never
-// wait on each other and need no atomics.
 // ---------------------------------------------------------------------------
-// Per-visibility record of the gridder's phase 2: weighted value and the
-// row bases of its padded u and v kernel rows (one 16-byte read in FP32).
-template <typename R> struct GridRec {
-    Cx<R> d;
-    int2 bs;
-};
 
 // Highest polynomial degree the planner picks for a support of ALPHA cells
 // (Sect. 4.2 uses ALPHA + 3); the kernels stage the coefficient table in LDS.
 template <int ALPHA> constexpr int kMaxDegree = ALPHA + 3;
 template <typename R, int ALPHA> constexpr size_t kCoefBytes = (size_t)(kMaxDegree<ALPHA> + 1) * ALPHA * sizeof(R);
-
-template <typename R, int ALPHA, int PS> struct GridStage {
-    static constexpr int CH = 256;                 // visibilities per chunk (one per phase-1 thread)
-    static constexpr int S = CH + 1;               // + one zero slot used as padding
-    static constexpr int KP = ALPHA + 6;           // padded kernel row
-    static constexpr int NKP = S * KP + 16;        // padded rows + zero tail for the padding slot
-    static constexpr int NREG = 16;                // 4x4-cell regions of a tile
-    static constexpr int LST = CH + 8;             // list capacity: entries + padding
-    static constexpr size_t al(size_t x) { return (x + 15) & ~(size_t)15; }
-    static constexpr size_t off_kv = al((size_t)NKP * sizeof(R));
-    static constexpr size_t off_kw = al(off_kv + (size_t)NKP * sizeof(R));
-    static constexpr size_t off_rec = al(off_kw + (size_t)S * PS * sizeof(R));
-    static constexpr size_t off_list = al(off_rec + (size_t)S * sizeof(GridRec<R>));
-    static constexpr size_t off_cnt = al(off_list + (size_t)NREG * LST * sizeof(uint16_t));
-    static constexpr size_t off_coef = al(off_cnt + (size_t)NREG * 4 * sizeof(int));
-    static constexpr size_t bytes = off_coef + kCoefBytes<R, ALPHA>;
-};
 
 // The w weights of one visibility on the batch's plane slots: slot rr holds
 // kernel cell rr + sh (zero outside [0, ALPHA)), for a shift sh in
@@ -111,47 +73,6 @@ __device__ __forceinline__ void rotate_w(const R kw[ALPHA], int sh, R out[PS]) {
     }
 #pragma unroll
     for (int rr = 0; rr < PS; ++rr) out[rr] = e[rr];
-}
-
-// Swaps across lane rows (gfx950 v_permlane32_swap / v_permlane16_swap):
-// swap32 exchanges lanes 32..63 of x with lanes 0..31 of y; swap16 exchanges
-// rows 1 and 3 of x with rows 0 and 2 of y.  FP64 values swap as two halves.
-__device__ __forceinline__ void swap32(float &x, float &y) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-    x = __uint_as_float(r[0]);
-    y = __uint_as_float(r[1]);
-}
-__device__ __forceinline__ void swap16(float &x, float &y) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-    x = __uint_as_float(r[0]);
-    y = __uint_as_float(r[1]);
-}
-__device__ __forceinline__ void swap32(double &x, double &y) {
-    const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
-    const unsigned long long by = (unsigned long long)__double_as_longlong(y);
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
-    x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-    y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
-__device__ __forceinline__ void swap16(double &x, double &y) {
-    const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
-    const unsigned long long by = (unsigned long long)__double_as_longlong(y);
-    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
-    x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
-    y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
-}
-// Row g of the result holds (a_g0 + a_g2) + (a_g1 + a_g3) for the value a
-// of region g: v0..v3 are the four regions' partial sums in every row.
-template <typename R> __device__ __forceinline__ R reduce_scatter4(R v0, R v1, R v2, R v3) {
-    swap32(v0, v2);               // v0: rows 0,1 of region 0 | rows 0,1 of region 2 ...
-    const R z0 = v0 + v2;         // rows 0,1: region 0 (g0+g2, g1+g3); rows 2,3: region 2
-    swap32(v1, v3);
-    const R z1 = v1 + v3;         // rows 0,1: region 1; rows 2,3: region 3
-    R a = z0, b = z1;
-    swap16(a, b);                 // a: rows (z0 r0, z1 r0, z0 r2, z1 r2); b: rows 1 / 3
-    return a + b;
 }
 
 // Block -> work item.  Blocks [0, pad8(n_extra)) take the listed extra items
@@ -223,215 +144,11 @@ __device__ __forceinline__ void footprint_masks(int2 an, int A, int B, const Geo
         if (lb0 <= 4 * q + 3 && lb0 + ALPHA > 4 * q) cm |= 1 << q;
     }
 }
-// Per-region lists of a chunk: region rg = (tile rows 4 (rg >> 2) ..,
-// columns 4 (rg & 3) ..) lists, in thread order, the chunk slots whose
-// footprint meets it.  The regions a footprint meets form the product of
-// its row and column masks, so the wave ballots of the 16 regions are
-// products of 4 row and 4 column ballots.  Every list is padded with the
-// zero slot (index CH) to a multiple of 4 plus the 4 entries read ahead by
-// the last step.  Ends with a barrier; s_cnt[rg * 4 + wave] holds the counts.
-template <int CH, int LST>
-__device__ __forceinline__ void build_region_lists(int bm, int cm, int tid, int lane, int wave, int *s_cnt,
-                                                   uint16_t *s_list) {
-    unsigned long long balr[4], balc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        balr[q] = __ballot((bm >> q) & 1);
-        balc[q] = __ballot((cm >> q) & 1);
-    }
-    if (lane < 16) {                                           // lane rg: this wave's count in region rg
-        const int qr = lane >> 2, qc = lane & 3;
-        unsigned long long br = balr[0], bc = balc[0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            br = qr == q ? balr[q] : br;
-            bc = qc == q ? balc[q] : bc;
-        }
-        s_cnt[lane * 4 + wave] = (int)__popcll(br & bc);
-    }
-    __syncthreads();
-    // lane rg: where this wave's entries of region rg start
-    int my_off = 0;
-    if (lane < 16) {
-        const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + lane * 4);
-        my_off = (wave > 0 ? c4.x : 0) + (wave > 1 ? c4.y : 0) + (wave > 2 ? c4.z : 0);
-    }
-#pragma unroll
-    for (int rg = 0; rg < 16; ++rg) {
-        const unsigned long long bal = balr[rg >> 2] & balc[rg & 3];
-        const int off = __builtin_amdgcn_readlane(my_off, rg);
-        // rank among this wave's members + the wave's offset
-        const int at = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)off));
-        if ((bm >> (rg >> 2)) & (cm >> (rg & 3)) & 1) s_list[rg * LST + at] = (uint16_t)tid;
-    }
-    if (tid < 16 * 8) {
-        const int rg = tid >> 3, k = tid & 7;
-        const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
-        const int n = c4.x + c4.y + c4.z + c4.w;
-        if (n + k < ((n + 3) & ~3) + 4) s_list[rg * LST + n + k] = (uint16_t)CH;
-    }
-    __syncthreads();
-}
-
-template <typename R, int ALPHA, int PS>
-__global__ __launch_bounds__(256) void k_grid(VisArgs<R> a, int J, const int4 *__restrict__ extra, int n_extra,
-                                              int cap, Cx<R> *__restrict__ G, Cx<R> *__restrict__ part) {
-    using C = Cx<R>;
-    using ST = GridStage<R, ALPHA, PS>;
-    constexpr int CH = ST::CH, KP = ST::KP;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *s_ku = reinterpret_cast<R *>(smem_raw);                         // [S][KP] + tail
-    R *s_kv = reinterpret_cast<R *>(smem_raw + ST::off_kv);            // [S][KP] + tail
-    R *s_kw = reinterpret_cast<R *>(smem_raw + ST::off_kw);            // [S][PS]
-    GridRec<R> *s_rec = reinterpret_cast<GridRec<R> *>(smem_raw + ST::off_rec);   // [S]
-    uint16_t *s_list = reinterpret_cast<uint16_t *>(smem_raw + ST::off_list);   // [16][LST]
-    int *s_cnt = reinterpret_cast<int *>(smem_raw + ST::off_cnt);      // [16 regions][4 waves]
-    R *s_coef = reinterpret_cast<R *>(smem_raw + ST::off_coef);        // [degree + 1][ALPHA]
-
-    const Geom &g = a.g;
-    int4 item;                                                 // (tile, first, count, slot or -1)
-    if (!work_item(extra, n_extra, g.ntu * g.ntv, cap, item)) return;
-    const int tile = item.x;
-    const int A = tile / g.ntv, B = tile - (tile / g.ntv) * g.ntv;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int grp = lane >> 4, cell = lane & 15;
-    const int row = 4 * wave + (cell >> 2);                    // this lane's tile row
-    const int cc = cell & 3;                                   // column within a region
-    const int j_lo = J * a.P;
-    const int j_hi = min(j_lo + a.P, g.nw);
-    const TileBins tb = tile_bins(a, J, A, B);
-    // this item's share of the concatenated list
-    const uint32_t first = (uint32_t)item.y;
-    const uint32_t last = min(tb.total, first + (uint32_t)item.z);
-    // the padding slot contributes nothing: zero value, zero kernel rows
-    if (tid == 0) {
-        GridRec<R> z;
-        z.d = cmake<C>((R)0, (R)0);
-        z.bs = make_int2(CH * KP, CH * KP);
-        s_rec[CH] = z;
-    }
-    for (int e = tid; e < (a.degree + 1) * ALPHA; e += CH) s_coef[e] = a.coef[e];
-    if (tid < KP + 16) {
-        s_ku[CH * KP + tid] = (R)0;
-        s_kv[CH * KP + tid] = (R)0;
-    }
-    if (tid < PS) s_kw[CH * PS + tid] = (R)0;
-    R acc_re[4][PS], acc_im[4][PS];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < PS; ++r) acc_re[q][r] = acc_im[q][r] = (R)0;
-    __syncthreads();                                           // coefficient table staged
-
-    for (uint32_t base = first; base < last; base += CH) {
-        // ---- phase 1: one thread per visibility -------------------------
-        const uint32_t pos = base + tid;
-        int bm = 0, cm = 0;                                    // tile rows / columns of 4 cells met
-        if (pos < last) {
-            const uint32_t s = tile_bins_pos(tb, pos);
-            const int2 an = a.anc[s];
-            const int iw = an.y & 0x7fffffff;
-            int la0, lb0;
-            footprint_masks<ALPHA>(an, A, B, g, la0, lb0, bm, cm);
-            GridRec<R> rec;
-            rec.d = a.vsorted[s];
-            rec.bs = make_int2(tid * KP - la0 + 3, tid * KP - lb0 + 3);
-            s_rec[tid] = rec;
-            const R zu = a.z[3 * (size_t)s], zv = a.z[3 * (size_t)s + 1], zw = a.z[3 * (size_t)s + 2];
-            R ku[ALPHA], kv[ALPHA], kw[ALPHA];
-            kernel_values_z3<ALPHA, R>(g.do_w, zu, zv, zw, s_coef, a.degree, ku, kv, kw);
-            R *pu = s_ku + tid * KP;
-            R *pv = s_kv + tid * KP;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                pu[i] = pv[i] = (R)0;
-                pu[ALPHA + 3 + i] = pv[ALPHA + 3 + i] = (R)0;
-            }
-#pragma unroll
-            for (int i = 0; i < ALPHA; ++i) {
-                pu[3 + i] = ku[i];
-                pv[3 + i] = kv[i];
-            }
-            // plane slot rr holds plane j_lo + rr, kernel cell j_lo + rr - iw
-            // (slots past the last plane of the batch are never stored)
-            if (g.do_w) {
-                R ws[PS];
-                rotate_w<R, ALPHA, PS>(kw, j_lo - iw, ws);
-#pragma unroll
-                for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = ws[rr];
-            } else {
-#pragma unroll
-                for (int rr = 0; rr < PS; ++rr) s_kw[tid * PS + rr] = (R)(rr == 0);
-            }
-        }
-        build_region_lists<CH, ST::LST>(bm, cm, tid, lane, wave, s_cnt, s_list);
-        // ---- phase 2: this wave's four regions, four visibilities a step --
-        // (software-pipelined: the next step's list entry and row bases are
-        // read while the current step accumulates)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rg = wave * 4 + q;
-            const int4 c4 = *reinterpret_cast<const int4 *>(s_cnt + rg * 4);
-            const int n4 = __builtin_amdgcn_readfirstlane((c4.x + c4.y + c4.z + c4.w + 3) & ~3);
-            const uint16_t *lst = s_list + rg * ST::LST + grp;
-            const int col = 4 * q + cc;
-            unsigned v = lst[0];
-            GridRec<R> rc = s_rec[v];
-            for (int j = 0; j < n4; j += 4) {
-                const R ku = s_ku[rc.bs.x + row], kv = s_kv[rc.bs.y + col];
-                const R *kwp = s_kw + v * PS;
-                R kw[PS];
-#pragma unroll
-                for (int r = 0; r < PS; ++r) kw[r] = kwp[r];
-                unsigned vn = lst[j + 4];
-                GridRec<R> rn = s_rec[vn];
-                const R wuv = ku * kv;
-                const R fr = rc.d.x * wuv, fi = rc.d.y * wuv;
-#pragma unroll
-                for (int r = 0; r < PS; ++r) {
-                    acc_re[q][r] += fr * kw[r];
-                    acc_im[q][r] += fi * kw[r];
-                }
-                // keep the read-ahead values in registers (not re-read from
-                // LDS at the top of the next step)
-                asm volatile("" : "+v"(vn), "+v"(rn.bs.x), "+v"(rn.bs.y), "+v"(rn.d.x), "+v"(rn.d.y));
-                v = vn;
-                rc = rn;
-            }
-        }
-        __syncthreads();
-    }
-    // reduce-scatter over the four lane groups (rows of 16 lanes): group k
-    // ends with the total of region k.  The cross-row swaps (gfx950): the
-    // 32-lane swap leaves rows (0,1 | 2,3) of two values as (x | y) and
-    // (x' | y'), the 16-lane swap rows (0 | 2) and (1 | 3); one add after each.
-    R tot_re[PS], tot_im[PS];
-#pragma unroll
-    for (int r = 0; r < PS; ++r) {
-        tot_re[r] = reduce_scatter4(acc_re[0][r], acc_re[1][r], acc_re[2][r], acc_re[3][r]);
-        tot_im[r] = reduce_scatter4(acc_im[0][r], acc_im[1][r], acc_im[2][r], acc_im[3][r]);
-    }
-    // lane group k stores region k of the wave's band: 4 rows x 16 columns
-    const int np = j_hi - j_lo;
-    const int colw = 4 * grp + cc;
-    C *dst;
-    int64_t pstride;
-    if (item.w < 0) {
-        dst = G + (int64_t)(A * kTileCells + row) * g.nv + (B * kTileCells + colw);
-        pstride = (int64_t)g.nu * g.nv;
-    } else {
-        dst = part + (size_t)item.w * a.P * kTileArea + row * kTileCells + colw;
-        pstride = kTileArea;
-    }
-#pragma unroll
-    for (int r = 0; r < PS; ++r)
-        if (r < np) dst[r * pstride] = cmake<C>(tot_re[r], tot_im[r]);
-}
-
 // ---------------------------------------------------------------------------
-// FP32 gridder on the matrix cores.  Same tiles and items as k_grid;
-// phase 2 is a matrix product per region.  For the four
+// The gridder on the matrix cores (FP32 and FP64).  Visibilities are taken
+// in chunks; phase 1, one lane per visibility, stages its kernel values,
+// operands and footprint masks in LDS; phase 2 is a matrix product per
+// 4x4-cell region of the tile.  For the four
 // visibilities k of a step and the 16 cells m of a region,
 //     D[n][m] += sum_k  dk_k[n] * (ku_k[row m] kv_k[col m]),
 // where n = 2 slot + (re, im) and dk_k[n] is the weighted visibility (its

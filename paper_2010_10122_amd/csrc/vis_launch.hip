@@ -19,13 +19,6 @@ inline unsigned item_blocks(const wg_plan *p, uint32_t n_extra) {
 
 template <typename R, int ALPHA> struct Launch {
     template <int PS>
-    static void grid_ps(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
-        const size_t lds = GridStage<R, ALPHA, PS>::bytes;
-        hipLaunchKernelGGL((k_grid<R, ALPHA, PS>), dim3(item_blocks(p, ne)), dim3(256), lds, st, va, J,
-                           p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
-    }
-    template <int PS>
     static void grid_mx(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
         const uint32_t ne = p->xg_off[J + 1] - p->xg_off[J];
         const size_t lds = GridStageMx1<R, ALPHA>::bytes;
@@ -33,13 +26,11 @@ template <typename R, int ALPHA> struct Launch {
                            p->xg + p->xg_off[J], (int)ne, kGridItemCap, G, part);
     }
     static void grid(const wg_plan *p, const VisArgs<R> &va, int J, Cx<R> *G, Cx<R> *part, hipStream_t st) {
-        // matrix cores, except for FP32 plans of a single plane (no w term),
-        // where 14 of their 16 plane-value rows would be idle; in FP64 the
-        // matrix-core form stays faster even then (Sect. 6.2 shape: 339
-        // against 462 ms a call)
-        if (p->P == 1 && sizeof(R) == 4)
-            grid_ps<1>(p, va, J, G, part, st);
-        else if (p->P > 4)
+        // matrix cores in every case; with a single plane (no w term) 14 of
+        // their 16 plane-value rows idle, and still the form measured faster
+        // than register FMAs (Sect. 6.2 shape: FP64 339 against 462 ms, FP32
+        // 55.7 against 69.0 ms a call)
+        if (p->P > 4)
             grid_mx<8>(p, va, J, G, part, st);
         else
             grid_mx<4>(p, va, J, G, part, st);
