@@ -91,3 +91,56 @@ def test_apply_graph_replays_equal_eager(dev, prec, eps, masked):
         assert torch.equal(outs[1], eager_i) and torch.equal(outs[3], eager_i)
     del g
     plan.close()
+
+
+def test_concurrent_calls_on_one_plan(dev):
+    """Two host threads apply one plan at once, each on its own stream with
+    its own workspace and outputs.  The calls share the plan's second stream
+    and its enqueue lock; every output must equal the single-stream result
+    bit for bit."""
+    import threading
+
+    import paper_2010_10122_amd as wg
+    rng = np.random.default_rng(23)
+    ant = synth.antennas_disk(rng, 16, 3000.0)
+    uvw_h = synth.earth_rotation_uvw(ant, 6.0, 30)[:3000]
+    freq_h = synth.channels(0.9e9, 1.7e9, 6)
+    npix = 192
+    pix = 6.0 * np.pi / 180 / npix
+    plan = wg.Plan(torch.from_numpy(uvw_h).to(dev), torch.from_numpy(freq_h).to(dev), npix, npix, pix, pix, 1e-5,
+                   "f32")
+    dirty = torch.from_numpy(rng.standard_normal((npix, npix))).to(dev, plan.real_dtype)
+    vis = torch.from_numpy(synth.complex_gaussian(rng, (uvw_h.shape[0], len(freq_h)))).to(dev, plan.complex_dtype)
+    ref_v = plan.degrid(dirty)
+    ref_i = plan.grid(vis)
+    torch.cuda.synchronize()
+    results, errors = {}, []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+            outs = []
+            for _ in range(3):
+                ov = torch.empty_like(ref_v)
+                oi = torch.empty_like(ref_i)
+                plan.degrid(dirty, out=ov, workspace=ws, stream=st)
+                plan.grid(vis, out=oi, workspace=ws, stream=st)
+                outs.append((ov, oi))
+            st.synchronize()
+            results[k] = outs
+        except Exception as e:          # reported by the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for k in range(2):
+        for ov, oi in results[k]:
+            assert torch.equal(ov, ref_v) and torch.equal(oi, ref_i)
+    print(f"[concurrent] {sum(len(r) for r in results.values())} call pairs equal", flush=True)
+    plan.close()
