@@ -22,6 +22,36 @@ def _header_functions():
     return sorted(set(re.findall(r"\b(wg_[a-z_]+)\s*\(", txt)))
 
 
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of wg_plan_desc and wg_plan_info_t have the
+    header's size and field offsets (a C program built against
+    include/wgrid.h prints them)."""
+    import shutil
+    import subprocess
+    from paper_2010_10122_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [("wg_plan_desc", _lib.PlanDesc), ("wg_plan_info_t", _lib.PlanInfo)]
+    lines = ["#include <stdio.h>", '#include "wgrid.h"', "int main(void) {"]
+    for cname, cls in structs:
+        lines.append(f'    printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True,
+                   capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs:
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2010_10122_amd import _lib
     lib = _lib.load()
